@@ -1,0 +1,214 @@
+/*
+ * shipwave.h -- C ABI of the MI355X (gfx950) library for steady nonlinear
+ * free-surface flow past a submerged source, solved by a preconditioned
+ * Jacobian-free Newton-Krylov method.
+ *
+ * Paper: Pethiyagoda, McCue, Moroney & Back, "Jacobian-free Newton-Krylov
+ * methods with GPU acceleration for computing nonlinear ship wave patterns".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh (numerical discretisation section): N points in x (x_1 .. x_N, spacing
+ * dx = (x_N - x_1)/(N-1)), M points in y (y_1 = 0 .. y_M, dy = y_M/(M-1)); the
+ * half domain y >= 0 with image terms.  Collocation points are the half-mesh
+ * points (x_{k+1/2}, y_l), k = 1..N-1, l = 1..M.
+ *
+ * Unknowns (reduced form of eq. unknowns): the first and third radiation
+ * equations (E3, E5 of Appendix A) are solved for phi_{1,l} and zeta_{1,l},
+ * which leaves 2NM unknowns, x fastest within each row l:
+ *     u = [ (phi_x)_{1..N,1}, ..., (phi_x)_{1..N,M}, (zeta_x)_{1..N,1}, ..., (zeta_x)_{1..N,M} ].
+ * Residual, same length and row layout (Appendix A order with E3/E5 removed):
+ *     E = [ E4_l, E1_{1..N-1,l} ]_{l=1..M}, [ E6_l, E2_{1..N-1,l} ]_{l=1..M}.
+ * E1 is the Bernoulli condition (eq. freeSurfCond), E2 the boundary-integral
+ * equation (eq. IntegroEqn) with the singular part of the second integral
+ * subtracted (eq. I2DashDash, S2) and added back in closed form (eq. IS2),
+ * E4/E6 the upstream radiation rows (eq. numUpRadiation, forward difference).
+ *
+ * Memory: every vector argument is device memory owned by the caller (for
+ * example torch tensors), FP64, contiguous.  The library never keeps a caller
+ * pointer after the call's stream work has completed.  Library-owned objects
+ * (sw_precond, sw_server) are released only by their destroy call.
+ *
+ * Streams: every call enqueues its work on `stream` and returns without
+ * waiting, except shipwave_solve and the server calls, which wait on their own
+ * stream for scalar control.  Internal scratch memory is kept per (device,
+ * stream); it grows on demand (hipMalloc, after a stream synchronisation).
+ * Calls on one stream are ordered by the stream; calls on different streams
+ * use different scratch and may run concurrently.
+ *
+ * Errors: return 0 (SW_OK) or a negative SW_E* code; no exception crosses the
+ * ABI and nothing exits the process.  shipwave_last_error() returns a message
+ * for the calling thread's most recent failure.
+ */
+#ifndef SHIPWAVE_H
+#define SHIPWAVE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHIPWAVE_ABI_VERSION 1
+
+enum {
+    SW_OK = 0,
+    SW_EINVAL = -1,      /* invalid argument (sizes, domain, parameters, null pointer) */
+    SW_ENOMEM = -2,      /* device allocation failed, or a request cannot be admitted */
+    SW_EHIP = -3,        /* HIP runtime error */
+    SW_ENOCONV = -4,     /* Newton did not converge (iteration limit or line-search failure) */
+    SW_ENONFINITE = -5,  /* a residual norm was NaN or Inf */
+    SW_EBUSY = -6        /* server: result not ready yet */
+};
+
+enum { SW_WEIGHTS_TRAPEZOID = 0, SW_WEIGHTS_SIMPSON = 1 };
+/* Spline end conditions for zeta_y, phi_y (the paper does not state them):
+ * 0 = zero slope at y = 0 (zeta, phi even in y) and not-a-knot at y_M;
+ * 1 = not-a-knot at both ends. */
+enum { SW_SPLINE_CLAMPED0 = 0, SW_SPLINE_NOTAKNOT = 1 };
+/* Arithmetic of the all-pairs sum: 0 = FP64; 1 = FP32 with Kahan-compensated
+ * row sums (grid fields, the closed-form I and the assembly stay FP64). */
+enum { SW_PREC_FP64 = 0, SW_PREC_FP32 = 1 };
+
+typedef struct { int32_t N, M; } sw_mesh;
+/* Truncated domain x_1 <= x <= x_N, 0 <= y <= y_M (section on discretisation). */
+typedef struct { double x1, xN, yM; } sw_domain;
+/* F: depth-based Froude number (eq. Froude); eps: source strength (eq. epsilon);
+ * nu: upstream decay constant of the radiation condition (0.05 in the paper). */
+typedef struct {
+    double F, eps, nu;
+    int32_t weights;     /* SW_WEIGHTS_*; Simpson needs odd N and M */
+    int32_t spline_bc;   /* SW_SPLINE_* */
+    int32_t precision;   /* SW_PREC_* */
+    int32_t reserved;
+} sw_params;
+typedef struct { sw_mesh mesh; sw_domain domain; sw_params params; } sw_problem;
+
+/* Validation shared by all calls: N, M >= 4; N <= 1024; F > 0; eps >= 0;
+ * nu > 0; x_1 < 0 < x_N is not required, but x_1 < x_N, y_M > 0; Simpson needs
+ * odd N and M.  Violations return SW_EINVAL. */
+
+int32_t shipwave_abi_version(void);
+const char* shipwave_last_error(void);
+
+/* E(u): the nonlinear residual of section 3 (steps: unpack + eliminate E3/E5,
+ * trapezoid integration in x (eq. zetaapprox), cubic spline in y, two-point
+ * interpolation to the half mesh, Bernoulli E1, closed-form I, the all-pairs
+ * boundary-integral sum, E2 assembly, radiation rows E4/E6).
+ * u, E: device, 2NM doubles each; must not overlap.  prob->params.precision
+ * selects the arithmetic of the all-pairs sum. */
+int32_t shipwave_residual(const sw_problem* prob, const double* u, double* E, hipStream_t stream);
+
+/* E(u) for nb independent problems (each with its own mesh, F, eps, precision),
+ * evaluated by shared launches: one prelude launch per kernel over all
+ * problems and one all-pairs launch over a combined work list.  probs: host
+ * array of nb problems; u, E: host arrays of nb device pointers.  Each
+ * result is bitwise identical to shipwave_residual on that problem alone. */
+int32_t shipwave_residual_batched(int32_t nb, const sw_problem* probs, const double* const* u,
+                                  double* const* E, hipStream_t stream);
+
+/* Jacobian-vector product by a first-order difference quotient (eq. JvApprox):
+ * Jz = (E(u + h z) - Eu) / h.  Eu must be E(u) computed with the same
+ * precision setting.  h <= 0 selects h = sqrt(macheps) (1 + ||u||_2) / ||z||_2
+ * (macheps of the pair-sum precision).  u, Eu, z, Jz: device, 2NM doubles;
+ * Jz may not alias u or z.  A zero z gives Jz = 0. */
+int32_t shipwave_jvp(const sw_problem* prob, const double* u, const double* Eu, const double* z,
+                     double h, double* Jz, hipStream_t stream);
+
+/* Preconditioner from the linear Jacobian (preconditioning section; Appendix B
+ * entries PreA-PreD; Appendix C storage): P = [[A, B], [C, D_q]] with A, B, C
+ * block diagonal (identical N x N blocks) and D_q the linear D with the blocks
+ * |l - m| <= q_blocks kept (block bandwidth b = 2 q_blocks + 1; q_blocks >=
+ * M - 1 keeps all of D).  Set-up forms the Schur complement
+ * S = D_q - C A^{-1} B and factorises it by block LU (FP64; partial pivoting
+ * inside each N x N diagonal block).  P depends on the mesh, domain, F, nu and
+ * weights, not on eps or u.  *out receives a library-owned handle. */
+typedef struct sw_precond sw_precond;
+int32_t shipwave_precond_build_banded(const sw_problem* prob, int32_t q_blocks, sw_precond** out,
+                                      hipStream_t stream);
+/* x = P^{-1} b by the three-step block solve of Appendix C.  b, x: device,
+ * 2NM doubles; may alias. */
+int32_t shipwave_precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t stream);
+void shipwave_precond_destroy(sw_precond* P);
+
+typedef struct {
+    double tol;            /* stop when ||E||_inf <= tol (default 1e-10) */
+    int32_t max_newton;    /* default 50 */
+    int32_t gmres_restart; /* Krylov dimension m before restart (default 30) */
+    int32_t max_gmres;     /* GMRES iterations per Newton step (default 200) */
+    int32_t q_blocks;      /* preconditioner block half-bandwidth (default 1; <0 -> default) */
+    int32_t precision;     /* SW_PREC_FP64, or SW_PREC_FP32: FP32-Kahan inner JVPs, FP64 outer */
+    int32_t weights;       /* SW_WEIGHTS_* */
+    int32_t spline_bc;     /* SW_SPLINE_* */
+    int32_t init;          /* 0: flat surface initial guess; 1: caller's u_inout */
+    double nu;             /* 0 -> 0.05 */
+    double eta_max;        /* Eisenstat-Walker forcing cap (default 0.9; <=0 -> default) */
+    const sw_precond* precond; /* optional prebuilt preconditioner for this mesh/F; NULL -> build */
+} sw_solve_opts;
+
+typedef struct {
+    int32_t status;        /* SW_OK, SW_ENOCONV, SW_ENONFINITE, ... */
+    int32_t newton_iters;
+    int32_t gmres_iters;
+    int32_t residual_evals;/* all E evaluations (Newton, JVP and line-search points) */
+    double final_norm;     /* ||E||_inf in FP64 at the returned u */
+    double time_total_s;
+    double time_precond_s; /* preconditioner set-up time (0 if supplied) */
+} sw_solve_info;
+
+/* Fill opts with the defaults above. */
+void shipwave_solve_opts_default(sw_solve_opts* opts);
+
+/* Solve E(u) = 0 for (F, eps) on the given mesh and domain by damped Newton
+ * (eq. newtonstep0) with a line search, the Newton step from right-
+ * preconditioned GMRES (Jacobian-free, eq. JvApprox) with Eisenstat-Walker
+ * forcing.  u_inout: device, 2NM doubles; initial guess if opts->init == 1,
+ * overwritten with the result (the best iterate on failure).  zeta_out:
+ * device N*M doubles (row-major [l][k]) or NULL: the surface heights.
+ * info_out: host, may be NULL.  Synchronises `stream`.  opts may be NULL
+ * (defaults). */
+int32_t shipwave_solve(double F, double eps, const sw_mesh* mesh, const sw_domain* domain,
+                       const sw_solve_opts* opts, double* u_inout, double* zeta_out,
+                       sw_solve_info* info_out, hipStream_t stream);
+
+/* Surface heights zeta_{k,l} ([l][k], N*M doubles, device) of a state u. */
+int32_t shipwave_zeta(const sw_problem* prob, const double* u, double* zeta, hipStream_t stream);
+
+/* ---- serving: continuous batching of many solves on one GPU ------------ */
+typedef struct sw_server sw_server;
+typedef struct {
+    double hbm_budget_bytes;  /* device memory the server may hold for admitted solves */
+    int32_t max_slots;        /* solves advanced together */
+    int32_t fallback_fp64;    /* 1: a mixed-precision solve that fails is retried in FP64 */
+    double tol;               /* Newton tolerance (default 1e-10) */
+    int32_t q_blocks;         /* preconditioner half-bandwidth (default 1) */
+    int32_t precision;        /* SW_PREC_* of the inner JVPs */
+} sw_server_opts;
+typedef struct {
+    sw_mesh mesh;
+    sw_domain domain;
+    double F, eps;
+} sw_request;
+typedef struct {
+    int32_t status;
+    int32_t newton_iters, gmres_iters, residual_evals;
+    int32_t used_fallback;
+    double final_norm;
+    double t_submit_s, t_admit_s, t_done_s; /* seconds on the server clock */
+} sw_result;
+
+int32_t shipwave_server_create(const sw_server_opts* opts, sw_server** out);
+/* Queue one request; returns a ticket.  The server copies the request. */
+int32_t shipwave_server_submit(sw_server* s, const sw_request* req, uint64_t* ticket);
+/* SW_OK with *res filled (and zeta copied to zeta_host if non-NULL, N*M
+ * doubles) once done, SW_EBUSY while pending, SW_EINVAL for an unknown ticket. */
+int32_t shipwave_server_poll(sw_server* s, uint64_t ticket, sw_result* res, double* zeta_host);
+/* Block until every submitted request is done. */
+int32_t shipwave_server_drain(sw_server* s);
+void shipwave_server_destroy(sw_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHIPWAVE_H */

@@ -268,7 +268,7 @@ def bernoulli(prob: Problem, f: Fields):
     return 0.5 * num / (1.0 + zx * zx + zy * zy) + f.zs / (prob.F * prob.F) - 0.5
 
 
-def pair_sum(geom: _Geom, f: Fields, *, block: int = 64, want_abs: bool = False):
+def pair_sum(geom: _Geom, f: Fields, *, block: int = 64, want_abs: bool = False, cols=None):
     """Sigma_{k,l} = sum_{i,j} w(i,j) [ (psi_ij - psi*) K1 + zeta_x,ij K2 - zeta_x* S2 ].
 
     The sum over every grid point (i,j) of the truncated domain for every
@@ -276,7 +276,9 @@ def pair_sum(geom: _Geom, f: Fields, *, block: int = 64, want_abs: bool = False)
     part zeta_x* S2 subtracted (numerical discretisation section).
     Offsets come from integers: x_i - x*_k = (i - k - 1/2) dx,
     y_j - y*_l = (j - l) dy and y_j + y*_l = (j + l) dy (row offsets).
-    Returns (Sigma, sum of |terms| per part) when want_abs.
+    Returns (Sigma, sum of |terms| per part) when want_abs.  With cols (flat
+    collocation indices l*(N-1) + k) only those points are summed; the rest
+    of the returned array is NaN.
     """
     N, R = geom.N, geom.R
     Nc = N - 1
@@ -296,11 +298,11 @@ def pair_sum(geom: _Geom, f: Fields, *, block: int = 64, want_abs: bool = False)
     A = 1.0 + zxs * zxs
     B = 2.0 * zxs * zys
     C = 1.0 + zys * zys
-    out = np.empty(Nc * R, dtype=np.result_type(psi, zeta, zx, zy))
-    mags = np.zeros((3, Nc * R)) if want_abs else None
-    for p0 in range(0, Nc * R, block):
-        p1 = min(p0 + block, Nc * R)
-        sl = slice(p0, p1)
+    out = np.full(Nc * R, np.nan, dtype=np.result_type(psi, zeta, zx, zy))
+    mags = np.full((3, Nc * R), np.nan) if want_abs else None
+    todo = np.arange(Nc * R) if cols is None else np.asarray(cols, dtype=np.int64)
+    for p0 in range(0, todo.size, block):
+        sl = todo[p0:p0 + block]
         dx = (si[None, :] - ck[sl, None] - 0.5) * geom.dx
         dy = (sj[None, :] - cl[sl, None]) * geom.dy
         dyp = (sj[None, :] + cl[sl, None]) * geom.dy
@@ -334,7 +336,7 @@ def _I_field(geom: _Geom, f: Fields):
     return I_closed(A, B, C, a1, a2, b1, b2, ystar, geom.yhi, geom.images)
 
 
-def _residual_geom(prob: Problem, geom: _Geom, psix, zetax, want_parts=False):
+def _residual_geom(prob: Problem, geom: _Geom, psix, zetax, want_parts=False, cols=None):
     f = grid_fields(prob, geom, psix, zetax)
     E1 = bernoulli(prob, f)
     xs = geom.x1 + (np.arange(geom.N - 1) + 0.5) * geom.dx
@@ -342,9 +344,9 @@ def _residual_geom(prob: Problem, geom: _Geom, psix, zetax, want_parts=False):
     src = prob.eps / np.sqrt(xs[None, :] ** 2 + ys[:, None] ** 2 + (f.zs + 1.0) ** 2)
     I = _I_field(geom, f)
     if want_parts:
-        Sig, mags = pair_sum(geom, f, want_abs=True)
+        Sig, mags = pair_sum(geom, f, want_abs=True, cols=cols)
     else:
-        Sig = pair_sum(geom, f)
+        Sig = pair_sum(geom, f, cols=cols)
     E2 = TWO_PI * f.ps + src - Sig - f.zxs * I
     x1, dx, nu = prob.x1, geom.dx, prob.nu
     E4 = x1 * (psix[:, 1] - psix[:, 0]) / dx + nu * psix[:, 0]
@@ -368,17 +370,41 @@ def residual(prob: Problem, u):
     return pack(E1, E2, E4, E6)
 
 
-def residual_parts(prob: Problem, u):
+def residual_parts(prob: Problem, u, cols=None):
     """Residual plus intermediate fields and per-row magnitudes (real u only)."""
     psix, zetax = unpack(prob, u)
-    return _residual_geom(prob, _half_geom(prob), psix, zetax, want_parts=True)
+    return _residual_geom(prob, _half_geom(prob), psix, zetax, want_parts=True, cols=cols)
+
+
+def e2_index_to_col(prob: Problem, idx):
+    """Index into E (must be an E2 entry) -> flat collocation index l*(N-1) + k."""
+    idx = np.asarray(idx) - prob.N * prob.M
+    l, r = np.divmod(idx, prob.N)
+    if np.any(idx < 0) or np.any(r == 0):
+        raise ValueError("not an E2 entry")
+    return l * (prob.N - 1) + (r - 1)
+
+
+def residual_rows(prob: Problem, u, rows):
+    """E(u)[rows] and row_scale(u)[rows], computing the all-pairs sum only at the
+    collocation points that the requested E2 entries need."""
+    rows = np.asarray(rows)
+    NM = prob.N * prob.M
+    e2 = rows[(rows >= NM) & ((rows - NM) % prob.N != 0)]
+    cols = e2_index_to_col(prob, e2) if e2.size else np.zeros(0, dtype=np.int64)
+    parts = residual_parts(prob, u, cols=cols)
+    E = pack(parts["E1"], parts["E2"], parts["E4"], parts["E6"])
+    return E[rows], _scale_from_parts(prob, parts)[rows]
 
 
 def row_scale(prob: Problem, u):
     """Per-equation magnitude: the sum of the absolute values of the terms that
     make up each residual entry, floored at 1.  A parity tolerance relative to
     this scale measures rounding against the size of what was summed."""
-    parts = residual_parts(prob, u)
+    return _scale_from_parts(prob, residual_parts(prob, u))
+
+
+def _scale_from_parts(prob: Problem, parts):
     f = parts["fields"]
     mags = parts["mags"]
     s2 = (mags.sum(axis=0) + np.abs(f.zxs * parts["I"]) + TWO_PI * np.abs(f.ps)
@@ -391,7 +417,7 @@ def row_scale(prob: Problem, u):
     psix, zetax = f.psix, f.zetax
     s4 = np.abs(x1 / dx) * (np.abs(psix[:, 1]) + np.abs(psix[:, 0])) + nu * np.abs(psix[:, 0])
     s6 = np.abs(x1 / dx) * (np.abs(zetax[:, 1]) + np.abs(zetax[:, 0])) + nu * np.abs(zetax[:, 0])
-    return np.maximum(1.0, pack(s1, s2, s4, s6))
+    return np.fmax(1.0, pack(s1, s2, s4, s6))
 
 
 def residual_full_domain(prob: Problem, psix_full, zetax_full):

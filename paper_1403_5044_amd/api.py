@@ -1,0 +1,208 @@
+"""Thin Python binding over libshipwave: argument marshalling only.
+
+Tensors are torch tensors on the GPU (float64, contiguous); the library works
+on their device pointers on the current torch stream.  Every numerical step
+runs in the HIP library; if it is not built, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, replace
+
+import torch
+
+from . import _lib as L
+
+WEIGHTS = {"trapezoid": 0, "simpson": 1}
+SPLINE = {"clamped0": 0, "notaknot": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Mesh N x M on [x1, xN] x [0, yM]; Froude number F, source strength eps."""
+    N: int
+    M: int
+    x1: float
+    xN: float
+    yM: float
+    F: float
+    eps: float
+    nu: float = 0.05
+    weights: str = "trapezoid"
+    spline_bc: str = "clamped0"
+    precision: str = "fp64"
+
+    @property
+    def n_unknowns(self) -> int:
+        return 2 * self.N * self.M
+
+    @property
+    def pairs(self) -> int:
+        """(collocation, grid) pairs in one all-pairs sum."""
+        return (self.N - 1) * self.M * self.N * self.M
+
+    def with_(self, **kw) -> "Problem":
+        return replace(self, **kw)
+
+    def c_struct(self) -> L.SwProblem:
+        p = L.SwProblem()
+        p.mesh.N, p.mesh.M = self.N, self.M
+        p.domain.x1, p.domain.xN, p.domain.yM = self.x1, self.xN, self.yM
+        p.params.F, p.params.eps, p.params.nu = self.F, self.eps, self.nu
+        p.params.weights = WEIGHTS[self.weights]
+        p.params.spline_bc = SPLINE[self.spline_bc]
+        p.params.precision = PRECISION[self.precision]
+        p.params.reserved = 0
+        return p
+
+
+def _lib():
+    return L.load()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, n: int, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous float64 with {n} elements")
+    return t.data_ptr()
+
+
+def residual(prob: Problem, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """E(u) (reduced Appendix-A order)."""
+    lib = _lib()
+    n = prob.n_unknowns
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=u.device)
+    ps = prob.c_struct()
+    L.check(lib.shipwave_residual(C.byref(ps), _dev(u, n, "u"), _dev(out, n, "E"), _stream()))
+    return out
+
+
+def residual_batched(probs, us, outs=None):
+    """E(u_b) for several problems in shared launches."""
+    lib = _lib()
+    nb = len(probs)
+    if outs is None:
+        outs = [torch.empty(p.n_unknowns, dtype=torch.float64, device=u.device)
+                for p, u in zip(probs, us)]
+    arr = (L.SwProblem * nb)(*[p.c_struct() for p in probs])
+    up = (C.c_void_p * nb)(*[_dev(u, p.n_unknowns, "u") for p, u in zip(probs, us)])
+    ep = (C.c_void_p * nb)(*[_dev(e, p.n_unknowns, "E") for p, e in zip(probs, outs)])
+    L.check(lib.shipwave_residual_batched(nb, arr, up, ep, _stream()))
+    return outs
+
+
+def jvp(prob: Problem, u, Eu, z, h: float = 0.0, out=None):
+    """(E(u + h z) - Eu) / h; h <= 0 picks the step from the norms of u and z."""
+    lib = _lib()
+    n = prob.n_unknowns
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=u.device)
+    ps = prob.c_struct()
+    L.check(lib.shipwave_jvp(C.byref(ps), _dev(u, n, "u"), _dev(Eu, n, "Eu"), _dev(z, n, "z"),
+                             float(h), _dev(out, n, "Jz"), _stream()))
+    return out
+
+
+def zeta(prob: Problem, u, out=None):
+    lib = _lib()
+    n = prob.n_unknowns
+    if out is None:
+        out = torch.empty(prob.N * prob.M, dtype=torch.float64, device=u.device)
+    ps = prob.c_struct()
+    L.check(lib.shipwave_zeta(C.byref(ps), _dev(u, n, "u"),
+                              _dev(out, prob.N * prob.M, "zeta"), _stream()))
+    return out
+
+
+class Preconditioner:
+    """Linear-Jacobian block preconditioner with block half-bandwidth q."""
+
+    def __init__(self, prob: Problem, q: int):
+        self.lib = _lib()
+        self.prob = prob
+        self.q = q
+        h = C.c_void_p()
+        ps = prob.c_struct()
+        L.check(self.lib.shipwave_precond_build_banded(C.byref(ps), int(q), C.byref(h), _stream()))
+        self.handle = h
+
+    def apply(self, b, out=None):
+        n = self.prob.n_unknowns
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=b.device)
+        L.check(self.lib.shipwave_precond_apply(self.handle, _dev(b, n, "b"), _dev(out, n, "x"),
+                                                _stream()))
+        return out
+
+    def close(self):
+        if self.handle:
+            torch.cuda.current_stream().synchronize()
+            self.lib.shipwave_precond_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    newton_iters: int
+    gmres_iters: int
+    residual_evals: int
+    final_norm: float
+    time_total_s: float
+    time_precond_s: float
+
+
+def solve_opts(**kw) -> L.SwSolveOpts:
+    lib = _lib()
+    o = L.SwSolveOpts()
+    lib.shipwave_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if k == "weights" and isinstance(v, str):
+            v = WEIGHTS[v]
+        if k == "spline_bc" and isinstance(v, str):
+            v = SPLINE[v]
+        if k == "precond":
+            v = v.handle if v is not None else None
+        setattr(o, k, v)
+    return o
+
+
+def solve(F: float, eps: float, N: int, M: int, x1: float, xN: float, yM: float, *,
+          u0=None, want_zeta: bool = True, check: bool = True, **opts):
+    """Newton-Krylov solve of E(u) = 0; returns (u, zeta or None, SolveInfo)."""
+    lib = _lib()
+    n = 2 * N * M
+    o = solve_opts(**opts)
+    if u0 is not None:
+        u = u0.clone()
+        o.init = 1
+    else:
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        o.init = 0
+    z = torch.empty(N * M, dtype=torch.float64, device=u.device) if want_zeta else None
+    mesh = L.SwMesh(N, M)
+    dom = L.SwDomain(x1, xN, yM)
+    info = L.SwSolveInfo()
+    rc = lib.shipwave_solve(float(F), float(eps), C.byref(mesh), C.byref(dom), C.byref(o),
+                            _dev(u, n, "u"), z.data_ptr() if z is not None else None,
+                            C.byref(info), _stream())
+    si = SolveInfo(info.status, info.newton_iters, info.gmres_iters, info.residual_evals,
+                   info.final_norm, info.time_total_s, info.time_precond_s)
+    if check and rc not in (0, -4):
+        L.check(rc)
+    return u, z, si

@@ -1,0 +1,168 @@
+// Memory-bound vector kernels for the Krylov solver: axpby, blocked dot
+// products (classical Gram-Schmidt), multi-vector updates and norms.
+// Reductions are two-pass with a grid size that depends only on n, so every
+// result is bitwise reproducible.
+#include "sw_internal.hpp"
+
+namespace sw {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int red_blocks(int n) {
+    int b = (n + kThreads * 4 - 1) / (kThreads * 4);
+    return b < 1 ? 1 : (b > 512 ? 512 : b);
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpby(int n, double a, const double* __restrict__ x,
+                                                    double b, const double* __restrict__ y,
+                                                    double* __restrict__ out) {
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        out[t] = fma(a, x[t], b * y[t]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(int n, double a, const double* __restrict__ x,
+                                                    double* __restrict__ out) {
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        out[t] = a * x[t];
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kThreads / 64; ++i) r = fmax(r, sh[i]);
+    __syncthreads();
+    return r;
+}
+
+// work[i * B + b] = partial dot of V_i and w over the block's grid-stride range
+__global__ __launch_bounds__(kThreads) void k_dots1(int n, const double* __restrict__ V,
+                                                    size_t ldv, const double* __restrict__ w,
+                                                    double* __restrict__ work) {
+    __shared__ double sh[kThreads / 64];
+    const int i = blockIdx.y;
+    const double* v = V + (size_t)i * ldv;
+    double s = 0.0;
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        s = fma(v[t], w[t], s);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) work[(size_t)i * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_dots2(int k, int B, const double* __restrict__ work, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += work[(size_t)i * B + b];
+    out[i] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemv_sub(int n, int k, const double* __restrict__ V,
+                                                       size_t ldv, const double* __restrict__ h,
+                                                       double* __restrict__ w) {
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+        double s = w[t];
+        for (int i = 0; i < k; ++i) s = fma(-h[i], V[(size_t)i * ldv + t], s);
+        w[t] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemv_acc(int n, int k, const double* __restrict__ V,
+                                                       size_t ldv, const double* __restrict__ y,
+                                                       double* __restrict__ out) {
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s = fma(y[i], V[(size_t)i * ldv + t], s);
+        out[t] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm1(int n, const double* __restrict__ x,
+                                                    double* __restrict__ work) {
+    __shared__ double sh[kThreads / 64];
+    double m = 0.0, s = 0.0;
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+        const double v = x[t];
+        // NaN propagates through the sum of squares; fmax would drop it
+        m = fmax(m, fabs(v));
+        s = fma(v, v, s);
+    }
+    m = block_max(m, sh);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        work[blockIdx.x] = m;
+        work[gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ void k_norm2(int B, const double* __restrict__ work, double* __restrict__ out2) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0, s = 0.0;
+    for (int b = 0; b < B; ++b) {
+        m = fmax(m, work[b]);
+        s += work[B + b];
+    }
+    // a non-finite sum of squares marks the max norm as non-finite too
+    out2[0] = (s == s && s <= 1.7976931348623157e308) ? m : s;
+    out2[1] = sqrt(s);
+}
+
+inline int ew_blocks(int n) {
+    int b = (n + kThreads - 1) / kThreads;
+    return b < 1 ? 1 : (b > 4096 ? 4096 : b);
+}
+
+}  // namespace
+
+size_t reduce_work_doubles(int n) { return (size_t)64 * red_blocks(n) + 64; }
+
+void axpby(int n, double a, const double* x, double b, const double* y, double* out,
+           hipStream_t s) {
+    k_axpby<<<ew_blocks(n), kThreads, 0, s>>>(n, a, x, b, y, out);
+}
+
+void scale_copy(int n, double a, const double* x, double* out, hipStream_t s) {
+    k_scale<<<ew_blocks(n), kThreads, 0, s>>>(n, a, x, out);
+}
+
+void dots(int n, int k, const double* V, size_t ldv, const double* w, double* out, double* work,
+          hipStream_t s) {
+    const int B = red_blocks(n);
+    k_dots1<<<dim3(B, k), kThreads, 0, s>>>(n, V, ldv, w, work);
+    k_dots2<<<(k + 63) / 64, 64, 0, s>>>(k, B, work, out);
+}
+
+void gemv_sub(int n, int k, const double* V, size_t ldv, const double* h, double* w,
+              hipStream_t s) {
+    k_gemv_sub<<<ew_blocks(n), kThreads, 0, s>>>(n, k, V, ldv, h, w);
+}
+
+void gemv_acc(int n, int k, const double* V, size_t ldv, const double* y, double* out,
+              hipStream_t s) {
+    k_gemv_acc<<<ew_blocks(n), kThreads, 0, s>>>(n, k, V, ldv, y, out);
+}
+
+void norm_inf_2(int n, const double* x, double* out2, double* work, hipStream_t s) {
+    const int B = red_blocks(n);
+    k_norm1<<<B, kThreads, 0, s>>>(n, x, work);
+    k_norm2<<<1, 64, 0, s>>>(B, work, out2);
+}
+
+}  // namespace sw

@@ -1,0 +1,553 @@
+// Nonlinear residual E(u) on gfx950.
+//
+// Steps (numerical discretisation section and Appendix A):
+//   k_scan      unknowns -> psi, zeta on the grid by trapezoidal integration in x
+//               (eq. zetaapprox), psi_1 and zeta_1 from the eliminated radiation
+//               rows E3/E5; the radiation rows E4/E6 (eq. numUpRadiation).
+//   k_spline    psi_y, zeta_y: slopes of the cubic spline through each column.
+//   k_points    source records of every grid point (fields pre-multiplied by the
+//               quadrature weight) and collocation records of every half-mesh
+//               point: two-point interpolation, Bernoulli E1 (eq. freeSurfCond),
+//               A, B, C, the closed form of I (eq. IS2), the submerged-source term.
+//   k_pairs_*   the all-pairs sum over every (collocation, grid) pair of
+//               w [(psi - psi*) K1 + zeta_x K2 - zeta_x* S2] (eq. IntegroEqn, S2),
+//               split over chunks of source rows; FP64 or FP32 + Kahan.
+//   k_finish    E2 = 2 pi psi* + source term - zeta_x* I - (sum over chunks).
+//
+// The all-pairs sum is bound by FP64 vector arithmetic, not memory: each lane
+// owns CP collocation points and sweeps a row of source records staged in LDS
+// (every lane reads the same record: an LDS broadcast).  The per-row terms
+// (y offsets and their products with B, C) are hoisted out of the source loop.
+#include "sw_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace sw {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip.  Map the
+// hardware block id to a work id such that each XCD receives a contiguous
+// range of work ids (and hence a contiguous range of source chunks, which then
+// share that XCD's L2).  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    constexpr int kXcd = 8;
+    const int xcd = b % kXcd;
+    const int idx = b / kXcd;
+    const int base = nblocks / kXcd;
+    const int rem = nblocks % kXcd;
+    return xcd * base + min(xcd, rem) + idx;
+}
+
+__device__ __forceinline__ double weight1d(int i, int n, int rule) {
+    if (rule == SW_WEIGHTS_TRAPEZOID) return (i == 0 || i == n - 1) ? 0.5 : 1.0;
+    if (i == 0 || i == n - 1) return 1.0 / 3.0;
+    return (i & 1) ? 4.0 / 3.0 : 2.0 / 3.0;
+}
+
+// ---- a1-a2: trapezoid integration in x, radiation rows -------------------------
+// One wavefront per (row l, field f): f = 0 -> psi from phi_x - 1, f = 1 -> zeta.
+__global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ u,
+                                             double* __restrict__ psi,
+                                             double* __restrict__ zeta,
+                                             double* __restrict__ E) {
+    const int l = blockIdx.x;
+    const int f = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int N = g.N;
+    const double* in = u + (size_t)f * g.NM + (size_t)l * N;
+    double* out = (f == 0 ? psi : zeta) + (size_t)l * N;
+    const double off = (f == 0) ? 1.0 : 0.0;
+    const double hdx = 0.5 * g.dx;
+    const int K = (N + 63) / 64;
+    const int a = min(lane * K, N);
+    const int b = min(a + K, N);
+    double tot = 0.0;
+    for (int m = a; m < b && m < N - 1; ++m) tot += hdx * ((in[m] - off) + (in[m + 1] - off));
+    double incl = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    const double fx0 = in[0] - off;
+    const double f1 = (-g.x1 / g.nu) * fx0;  // eliminated E3 / E5
+    double val = f1 + excl;
+    for (int k = a; k < b; ++k) {
+        out[k] = val;
+        if (k < N - 1) val += hdx * ((in[k] - off) + (in[k + 1] - off));
+    }
+    if (lane == 0) {
+        const double fx1 = in[1] - off;
+        E[(size_t)f * g.NM + (size_t)l * N] = g.x1 * (fx1 - fx0) / g.dx + g.nu * fx0;
+    }
+}
+
+// ---- a3: cubic-spline slopes in y ----------------------------------------------------
+// Tridiagonal form of the spline conditions (uniform knots, spacing h, slopes s):
+//   first knot:  clamped0: s_0 = 0;  not-a-knot: s_0 + 2 s_1 = (5 d_0 + d_1) / (2h)
+//   interior:    s_{j-1} + 4 s_j + s_{j+1} = 3 (f_{j+1} - f_{j-1}) / h
+//   last knot:   not-a-knot: 2 s_{M-2} + s_{M-1} = (d_{M-3} + 5 d_{M-2}) / (2h)
+// (d_j = f_{j+1} - f_j; the not-a-knot rows are the third-derivative
+// continuity conditions with the neighbouring interior row eliminated).
+// The elimination coefficients depend only on M and the end condition.
+__global__ void k_spline_setup(int M, int bc, double* __restrict__ spl) {
+    double* cp = spl;
+    double* minv = spl + M;
+    double c0 = (bc == SW_SPLINE_CLAMPED0) ? 0.0 : 2.0;
+    double m = 1.0;
+    minv[0] = 1.0 / m;
+    cp[0] = c0 / m;
+    for (int j = 1; j < M; ++j) {
+        const double aj = (j == M - 1) ? 2.0 : 1.0;
+        const double bj = (j == M - 1) ? 1.0 : 4.0;
+        const double cj = (j == M - 1) ? 0.0 : 1.0;
+        m = bj - aj * cp[j - 1];
+        minv[j] = 1.0 / m;
+        cp[j] = cj / m;
+    }
+}
+
+__global__ __launch_bounds__(128) void k_spline(Geo g, const double* __restrict__ spl,
+                                                const double* __restrict__ psi,
+                                                const double* __restrict__ zeta,
+                                                double* __restrict__ psiy,
+                                                double* __restrict__ zetay) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * g.N) return;
+    const int f = t / g.N;
+    const int k = t - f * g.N;
+    const int N = g.N, M = g.M;
+    const double* F = (f == 0 ? psi : zeta) + k;
+    double* S = (f == 0 ? psiy : zetay) + k;
+    const double* cp = spl;
+    const double* minv = spl + M;
+    const double h = g.dy;
+    const double r3h = 3.0 / h;
+    const double r2h = 0.5 / h;
+    double f0 = F[0], f1 = F[(size_t)N], f2 = F[(size_t)2 * N];
+    double d0 = (g.bc == SW_SPLINE_CLAMPED0) ? 0.0 : r2h * (5.0 * (f1 - f0) + (f2 - f1));
+    double dp = d0 * minv[0];
+    S[0] = dp;
+    double fm = f0, fc = f1;
+    for (int j = 1; j < M - 1; ++j) {
+        const double fp = F[(size_t)(j + 1) * N];
+        dp = (r3h * (fp - fm) - dp) * minv[j];
+        S[(size_t)j * N] = dp;
+        fm = fc;
+        fc = fp;
+    }
+    {
+        // fm = f_{M-3}... after the loop fm = f_{M-2}, fc = f_{M-1}
+        const double fmm = F[(size_t)(M - 3) * N];
+        const double dlast = r2h * ((fm - fmm) + 5.0 * (fc - fm));
+        dp = (dlast - 2.0 * dp) * minv[M - 1];
+    }
+    double s = dp;
+    S[(size_t)(M - 1) * N] = s;
+    for (int j = M - 2; j >= 0; --j) {
+        s = S[(size_t)j * N] - cp[j] * s;
+        S[(size_t)j * N] = s;
+    }
+}
+
+// ---- a4: closed form of I -----------------------------------------------------------
+// L(P,B,R;t) = int_0^t ds / sqrt(P s^2 + B s + R) = P^{-1/2} ln((2 sqrt(P) q(t) + 2Pt + B) /
+// (2 sqrt(PR) + B)), q(t) = sqrt(P t^2 + B t + R); a negative 2Pt + B (or B) is
+// handled through the conjugate (4PR - B^2) / (2 sqrt(P) q - 2Pt - B).
+__device__ double lint(double P, double B, double R, double disc, double t) {
+    const double sP = sqrt(P);
+    const double q = sqrt(fma(fma(P, t, B), t, R));
+    const double lin = fma(2.0 * P, t, B);
+    const double top = (lin >= 0.0) ? fma(2.0 * sP, q, lin) : disc / fma(2.0 * sP, q, -lin);
+    const double s0 = 2.0 * sqrt(P * R);
+    const double bot = (B >= 0.0) ? s0 + B : disc / (s0 - B);
+    return log(top / bot) / sP;
+}
+
+// G(a,b) = int_0^a int_0^b dY dX / sqrt(A X^2 + B X Y + C Y^2): the rectangle split on
+// its diagonal, Y = tX below and X = sY above.
+__device__ double grect(double A, double B, double C, double disc, double a, double b) {
+    if (!(a > 0.0) || !(b > 0.0)) return 0.0;
+    return a * lint(C, B, A, disc, b / a) + b * lint(A, B, C, disc, a / b);
+}
+
+__device__ double closed_form_I(double A, double B, double C, double disc, double a1, double a2,
+                                double ys, double yM) {
+    const double b1 = ys, b2 = yM - ys;
+    const double direct = grect(A, B, C, disc, a2, b2) + grect(A, -B, C, disc, a1, b2) +
+                          grect(A, -B, C, disc, a2, b1) + grect(A, B, C, disc, a1, b1);
+    const double yt = yM + ys;
+    const double image = (grect(A, -B, C, disc, a2, yt) + grect(A, B, C, disc, a1, yt)) -
+                         (grect(A, -B, C, disc, a2, ys) + grect(A, B, C, disc, a1, ys));
+    return direct + image;
+}
+
+// Source record (64 B): x, zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
+// FP32 source record (32 B): i (exact), zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
+// Collocation record (64 B): x*, y*, zeta*, psi*, zeta_x*, zeta_y*, E2 local part, -
+__global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict__ u,
+                                                const double* __restrict__ psi,
+                                                const double* __restrict__ zeta,
+                                                const double* __restrict__ psiy,
+                                                const double* __restrict__ zetay,
+                                                double* __restrict__ src64,
+                                                float* __restrict__ src32,
+                                                double* __restrict__ col,
+                                                double* __restrict__ E) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= g.NM) return;
+    const int l = gi / g.N;
+    const int k = gi - l * g.N;
+    const double* phx = u;
+    const double* zx = u + g.NM;
+    const double w = g.dx * g.dy * weight1d(k, g.N, g.weights) * weight1d(l, g.M, g.weights);
+    const double ps = psi[gi], ze = zeta[gi], zxv = zx[gi], zyv = zetay[gi];
+    {
+        double* r = src64 + (size_t)gi * 8;
+        const double x = g.x1 + k * g.dx;
+        reinterpret_cast<double4*>(r)[0] = make_double4(x, ze, zxv, zyv);
+        reinterpret_cast<double4*>(r)[1] = make_double4(w * ps, w, w * zxv, 0.0);
+        if (g.precision == SW_PREC_FP32) {
+            float* s = src32 + (size_t)gi * 8;
+            reinterpret_cast<float4*>(s)[0] =
+                make_float4((float)k, (float)ze, (float)zxv, (float)zyv);
+            reinterpret_cast<float4*>(s)[1] =
+                make_float4((float)(w * ps), (float)w, (float)(w * zxv), 0.0f);
+        }
+    }
+    if (k >= g.N - 1) return;
+    const int c = l * g.Nc + k;
+    const int g1 = gi + 1;
+    const double pxs = 0.5 * ((phx[gi] - 1.0) + (phx[g1] - 1.0));
+    const double pss = 0.5 * (ps + psi[g1]);
+    const double pys = 0.5 * (psiy[gi] + psiy[g1]);
+    const double zs = 0.5 * (ze + zeta[g1]);
+    const double zxs = 0.5 * (zxv + zx[g1]);
+    const double zys = 0.5 * (zyv + zetay[g1]);
+    // E1: Bernoulli condition with phi_x* = 1 + psi_x*, phi_y* = psi_y*
+    const double fx = 1.0 + pxs, fy = pys;
+    const double num = (1.0 + zxs * zxs) * fy * fy + (1.0 + zys * zys) * fx * fx -
+                       2.0 * zxs * zys * fx * fy;
+    const double den = 1.0 + zxs * zxs + zys * zys;
+    E[(size_t)l * g.N + k + 1] = 0.5 * num / den + zs / (g.F * g.F) - 0.5;
+    // Singular-part quadratic form and its exact integral
+    const double A = 1.0 + zxs * zxs, B = 2.0 * zxs * zys, C = 1.0 + zys * zys;
+    const double xs = g.x1 + (k + 0.5) * g.dx;
+    const double ys = l * g.dy;
+    const double I = closed_form_I(A, B, C, 4.0 * den, xs - g.x1, g.xN - xs, ys, g.yM);
+    const double zp1 = zs + 1.0;
+    const double srcterm = g.eps / sqrt(xs * xs + ys * ys + zp1 * zp1);
+    const double base = kTwoPi * pss + srcterm - zxs * I;
+    double* r = col + (size_t)c * 8;
+    reinterpret_cast<double4*>(r)[0] = make_double4(xs, ys, zs, pss);
+    reinterpret_cast<double4*>(r)[1] = make_double4(zxs, zys, base, 0.0);
+}
+
+// ---- a5: the all-pairs sum ----------------------------------------------------------
+// 1/sqrt(x) in FP64: hardware estimate plus one Newton-Raphson step,
+// y1 = y0 + y0 (1 - x y0^2) / 2, relative error 1.5 e0^2 for an estimate error e0.
+__device__ __forceinline__ double rsq64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+constexpr int kPairThreads = 256;
+
+template <int CP>
+__device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __restrict__ src,
+                                               const double* __restrict__ col,
+                                               double* __restrict__ partial, int tile, int chunk,
+                                               int G, double* lds) {
+    const int tid = threadIdx.x;
+    const int j0 = (int)((long long)chunk * g.M / G);
+    const int j1 = (int)((long long)(chunk + 1) * g.M / G);
+    const int N = g.N;
+    double xs[CP], zs[CP], ps[CP], zxs[CP], A[CP], B[CP], C[CP];
+    double acc1[CP], acc2[CP], acc3[CP];
+    int idx[CP], lrow[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+        idx[c] = tile * kPairThreads * CP + c * kPairThreads + tid;
+        const int li = min(idx[c], g.ncol - 1);
+        lrow[c] = li / g.Nc;
+        const double4 r0 = reinterpret_cast<const double4*>(col + (size_t)li * 8)[0];
+        const double4 r1 = reinterpret_cast<const double4*>(col + (size_t)li * 8)[1];
+        xs[c] = r0.x;
+        zs[c] = r0.z;
+        ps[c] = r0.w;
+        zxs[c] = r1.x;
+        const double zy = r1.y;
+        A[c] = 1.0 + r1.x * r1.x;
+        B[c] = 2.0 * r1.x * zy;
+        C[c] = 1.0 + zy * zy;
+        acc1[c] = acc2[c] = acc3[c] = 0.0;
+    }
+    for (int j = j0; j < j1; ++j) {
+        __syncthreads();
+        {
+            const double2* srow = reinterpret_cast<const double2*>(src + (size_t)j * N * 8);
+            double2* dst = reinterpret_cast<double2*>(lds);
+            for (int t = tid; t < N * 4; t += kPairThreads) dst[t] = srow[t];
+        }
+        __syncthreads();
+        double dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+            dy[c] = (double)(j - lrow[c]) * g.dy;
+            dyp[c] = (double)(j + lrow[c]) * g.dy;
+            dy2[c] = dy[c] * dy[c];
+            dyp2[c] = dyp[c] * dyp[c];
+            Bdy[c] = B[c] * dy[c];
+            mBdyp[c] = -B[c] * dyp[c];
+            Cdy2[c] = C[c] * dy2[c];
+            Cdyp2[c] = C[c] * dyp2[c];
+        }
+#pragma unroll 2
+        for (int i = 0; i < N; ++i) {
+            const double4 s0 = reinterpret_cast<const double4*>(lds + i * 8)[0];
+            const double4 s1 = reinterpret_cast<const double4*>(lds + i * 8)[1];
+            const double sx = s0.x, sz = s0.y, szx = s0.z, szy = s0.w;
+            const double swp = s1.x, sw = s1.y, swzx = s1.z;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+                const double dx = sx - xs[c];
+                const double dx2 = dx * dx;
+                const double dz = sz - zs[c];
+                const double h = fma(dz, dz, dx2);
+                const double i1 = rsq64(h + dy2[c]);
+                const double i2 = rsq64(h + dyp2[c]);
+                const double q1 = fma(dx, fma(A[c], dx, Bdy[c]), Cdy2[c]);
+                const double q2 = fma(dx, fma(A[c], dx, mBdyp[c]), Cdyp2[c]);
+                const double j1s = rsq64(q1);
+                const double j2s = rsq64(q2);
+                const double n0 = fma(-dx, szx, dz);
+                const double n1 = fma(-dy[c], szy, n0);
+                const double n2 = fma(-dyp[c], szy, n0);
+                const double K1 = fma(n1, i1 * i1 * i1, n2 * (i2 * i2 * i2));
+                const double wd = fma(-sw, ps[c], swp);
+                acc1[c] = fma(wd, K1, acc1[c]);
+                acc2[c] = fma(swzx, i1 + i2, acc2[c]);
+                acc3[c] = fma(sw, j1s + j2s, acc3[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+        if (idx[c] < g.ncol)
+            partial[(size_t)chunk * g.ncol + idx[c]] = acc1[c] + acc2[c] - zxs[c] * acc3[c];
+}
+
+template <int CP>
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f64(Geo g, const double* __restrict__ src,
+                                                            const double* __restrict__ col,
+                                                            double* __restrict__ partial,
+                                                            int ntiles, int G) {
+    extern __shared__ double lds[];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    pairs_f64_body<CP>(g, src, col, partial, w % ntiles, w / ntiles, G, lds);
+}
+
+// FP32 pair sum: the same terms in single precision.  Offsets come from exact
+// integers (i - k - 1/2 and j -+ l are exact in FP32), so the nearest pairs
+// keep full relative accuracy.  Each source row is summed in FP32 and the row
+// sums are added with Kahan compensation.
+__device__ __forceinline__ void kahan_add(float& s, float& comp, float v) {
+    const float y = __fsub_rn(v, comp);
+    const float t = __fadd_rn(s, y);
+    comp = __fsub_rn(__fsub_rn(t, s), y);
+    s = t;
+}
+
+template <int CP>
+__device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __restrict__ src,
+                                               const double* __restrict__ col,
+                                               double* __restrict__ partial, int tile, int chunk,
+                                               int G, float* lds) {
+    const int tid = threadIdx.x;
+    const int j0 = (int)((long long)chunk * g.M / G);
+    const int j1 = (int)((long long)(chunk + 1) * g.M / G);
+    const int N = g.N;
+    const float fdx = (float)g.dx;
+    float t0[CP], zs[CP], ps[CP], zxs[CP], A[CP], B[CP], C[CP];
+    float S[CP], comp[CP];
+    int idx[CP], lrow[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+        idx[c] = tile * kPairThreads * CP + c * kPairThreads + tid;
+        const int li = min(idx[c], g.ncol - 1);
+        lrow[c] = li / g.Nc;
+        const int kc = li - lrow[c] * g.Nc;
+        t0[c] = -((float)kc + 0.5f);
+        const double4 r0 = reinterpret_cast<const double4*>(col + (size_t)li * 8)[0];
+        const double4 r1 = reinterpret_cast<const double4*>(col + (size_t)li * 8)[1];
+        zs[c] = (float)r0.z;
+        ps[c] = (float)r0.w;
+        zxs[c] = (float)r1.x;
+        A[c] = (float)(1.0 + r1.x * r1.x);
+        B[c] = (float)(2.0 * r1.x * r1.y);
+        C[c] = (float)(1.0 + r1.y * r1.y);
+        S[c] = comp[c] = 0.0f;
+    }
+    for (int j = j0; j < j1; ++j) {
+        __syncthreads();
+        {
+            const float4* srow = reinterpret_cast<const float4*>(src + (size_t)j * N * 8);
+            float4* dst = reinterpret_cast<float4*>(lds);
+            for (int t = tid; t < N * 2; t += kPairThreads) dst[t] = srow[t];
+        }
+        __syncthreads();
+        float dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
+        float r1[CP], r2[CP], r3[CP];
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+            dy[c] = (float)(j - lrow[c]) * (float)g.dy;
+            dyp[c] = (float)(j + lrow[c]) * (float)g.dy;
+            dy2[c] = dy[c] * dy[c];
+            dyp2[c] = dyp[c] * dyp[c];
+            Bdy[c] = B[c] * dy[c];
+            mBdyp[c] = -B[c] * dyp[c];
+            Cdy2[c] = C[c] * dy2[c];
+            Cdyp2[c] = C[c] * dyp2[c];
+            r1[c] = r2[c] = r3[c] = 0.0f;
+        }
+#pragma unroll 2
+        for (int i = 0; i < N; ++i) {
+            const float4 s0 = reinterpret_cast<const float4*>(lds + i * 8)[0];
+            const float4 s1 = reinterpret_cast<const float4*>(lds + i * 8)[1];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+                const float dx = (s0.x + t0[c]) * fdx;
+                const float dx2 = dx * dx;
+                const float dz = s0.y - zs[c];
+                const float h = fmaf(dz, dz, dx2);
+                const float i1 = __builtin_amdgcn_rsqf(h + dy2[c]);
+                const float i2 = __builtin_amdgcn_rsqf(h + dyp2[c]);
+                const float q1 = fmaf(dx, fmaf(A[c], dx, Bdy[c]), Cdy2[c]);
+                const float q2 = fmaf(dx, fmaf(A[c], dx, mBdyp[c]), Cdyp2[c]);
+                const float j1s = __builtin_amdgcn_rsqf(q1);
+                const float j2s = __builtin_amdgcn_rsqf(q2);
+                const float n0 = fmaf(-dx, s0.z, dz);
+                const float n1 = fmaf(-dy[c], s0.w, n0);
+                const float n2 = fmaf(-dyp[c], s0.w, n0);
+                const float K1 = fmaf(n1, i1 * i1 * i1, n2 * (i2 * i2 * i2));
+                const float wd = fmaf(-s1.y, ps[c], s1.x);
+                r1[c] = fmaf(wd, K1, r1[c]);
+                r2[c] = fmaf(s1.z, i1 + i2, r2[c]);
+                r3[c] = fmaf(s1.y, j1s + j2s, r3[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CP; ++c) kahan_add(S[c], comp[c], (r1[c] + r2[c]) - zxs[c] * r3[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+        if (idx[c] < g.ncol)
+            partial[(size_t)chunk * g.ncol + idx[c]] = (double)S[c] - (double)comp[c];
+}
+
+template <int CP>
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f32(Geo g, const float* __restrict__ src,
+                                                            const double* __restrict__ col,
+                                                            double* __restrict__ partial,
+                                                            int ntiles, int G) {
+    extern __shared__ float ldsf[];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    pairs_f32_body<CP>(g, src, col, partial, w % ntiles, w / ntiles, G, ldsf);
+}
+
+// ---- a6: E2 assembly ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict__ col,
+                                                const double* __restrict__ partial, int G,
+                                                double* __restrict__ E) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncol) return;
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += partial[(size_t)q * g.ncol + c];
+    const int l = c / g.Nc;
+    const int k = c - l * g.Nc;
+    E[(size_t)g.NM + (size_t)l * g.N + k + 1] = col[(size_t)c * 8 + 6] - s;
+}
+
+__global__ __launch_bounds__(64) void k_zeta_rows(Geo g, const double* __restrict__ u,
+                                                  double* __restrict__ zeta) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= g.M) return;
+    const double* zx = u + g.NM + (size_t)l * g.N;
+    double* out = zeta + (size_t)l * g.N;
+    double v = (-g.x1 / g.nu) * zx[0];
+    out[0] = v;
+    for (int k = 0; k < g.N - 1; ++k) {
+        v += 0.5 * g.dx * (zx[k] + zx[k + 1]);
+        out[k + 1] = v;
+    }
+}
+
+constexpr int kCP64 = 2;
+constexpr int kCP32 = 2;
+
+}  // namespace
+
+int choose_chunks(const Geo& g) {
+    const int cp = (g.precision == SW_PREC_FP32) ? kCP32 : kCP64;
+    const int ntiles = (g.ncol + kPairThreads * cp - 1) / (kPairThreads * cp);
+    const int target = 4096;
+    int G = (target + ntiles - 1) / ntiles;
+    return std::max(1, std::min(G, g.M));
+}
+
+size_t residual_scratch_bytes(const Geo& g, int G) {
+    const size_t NM = g.NM, nc = g.ncol;
+    return carve_size({4 * NM * 8, NM * 64, (g.precision == SW_PREC_FP32 ? NM * 32 : 0), nc * 64,
+                       (size_t)G * nc * 8, (size_t)2 * g.M * 8});
+}
+
+ResidualBufs carve_residual(Carve& c, const Geo& g, int G) {
+    ResidualBufs b{};
+    const size_t NM = g.NM, nc = g.ncol;
+    double* grid = c.take<double>(4 * NM);
+    b.psi = grid;
+    b.zeta = grid + NM;
+    b.psiy = grid + 2 * NM;
+    b.zetay = grid + 3 * NM;
+    b.src64 = c.take<double>(NM * 8);
+    b.src32 = c.take<float>(g.precision == SW_PREC_FP32 ? NM * 8 : 0);
+    b.col = c.take<double>(nc * 8);
+    b.partial = c.take<double>((size_t)G * nc);
+    b.spl = c.take<double>((size_t)2 * g.M);
+    b.G = G;
+    return b;
+}
+
+void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBufs& b,
+                      hipStream_t s) {
+    k_scan<<<dim3(g.M, 2), 64, 0, s>>>(g, u, b.psi, b.zeta, E);
+    k_spline_setup<<<1, 1, 0, s>>>(g.M, g.bc, b.spl);
+    k_spline<<<(2 * g.N + 127) / 128, 128, 0, s>>>(g, b.spl, b.psi, b.zeta, b.psiy, b.zetay);
+    k_points<<<(g.NM + 255) / 256, 256, 0, s>>>(g, u, b.psi, b.zeta, b.psiy, b.zetay, b.src64,
+                                                 b.src32, b.col, E);
+    if (g.precision == SW_PREC_FP32) {
+        const int ntiles = (g.ncol + kPairThreads * kCP32 - 1) / (kPairThreads * kCP32);
+        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)g.N * 32, s>>>(
+            g, b.src32, b.col, b.partial, ntiles, b.G);
+    } else {
+        const int ntiles = (g.ncol + kPairThreads * kCP64 - 1) / (kPairThreads * kCP64);
+        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)g.N * 64, s>>>(
+            g, b.src64, b.col, b.partial, ntiles, b.G);
+    }
+    k_finish<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, b.col, b.partial, b.G, E);
+    SW_HIP(hipGetLastError());
+}
+
+void zeta_enqueue(const Geo& g, const double* u, double* zeta, hipStream_t s) {
+    k_zeta_rows<<<(g.M + 63) / 64, 64, 0, s>>>(g, u, zeta);
+    SW_HIP(hipGetLastError());
+}
+
+}  // namespace sw

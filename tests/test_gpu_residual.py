@@ -1,0 +1,151 @@
+"""Parity of the HIP residual E(u) (through the C ABI) against the FP64 oracle.
+
+Gate (FP64): |E_gpu - E_oracle| <= 1e-11 * scale per entry, where scale is the
+sum of the absolute values of the terms that make up that entry (floored at 1).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import residual as oresidual
+from oracle.equations import residual_rows, row_scale, zeta_grid
+from oracle.solve import jvp_complex, jvp_fd
+from paper_1403_5044_amd import api, inputs
+
+from gpu_common import dev, gprob, gpu_residual, host, log, oprob
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+SMALL_CASES = [
+    # (name, problem settings)
+    ("tiny9x5", dict(N=9, M=5, x1=-3.0, xN=3.0, yM=2.0, F=0.7, eps=0.3)),
+    ("config1", inputs.CONFIG1),
+    ("even40x9", dict(N=40, M=9, x1=-6.0, xN=5.0, yM=4.0, F=0.9, eps=0.2)),
+    ("simpson13x7", dict(N=13, M=7, x1=-4.0, xN=4.0, yM=3.0, F=0.7, eps=0.4,
+                         weights="simpson")),
+    ("notaknot61x21", dict(N=61, M=21, x1=-16.0, xN=8.0, yM=12.0, F=0.6, eps=0.2,
+                           spline_bc="notaknot")),
+    ("ragged97x13", dict(N=97, M=13, x1=-10.0, xN=14.0, yM=6.0, F=1.0, eps=0.1)),
+]
+
+
+def _check(name, p, u, E, tol=TOL64):
+    op = oprob(p)
+    Eo = oresidual(op, u)
+    sc = row_scale(op, u)
+    err = np.abs(E - Eo) / sc
+    log(f"{name}: max rel err {err.max():.3e} (entries {E.size})")
+    assert np.all(np.isfinite(E))
+    assert err.max() <= tol, (name, int(err.argmax()), err.max())
+    return err.max()
+
+
+@pytest.mark.parametrize("name,cfg", [("config1", inputs.CONFIG1), ("config2", inputs.CONFIG2)])
+def test_flat_state_without_source_is_exactly_zero(name, cfg):
+    p = gprob(cfg, eps=0.0)
+    E = gpu_residual(p, inputs.flat_state(p.N, p.M))
+    log(f"{name}: max |E| = {np.abs(E).max()}")
+    assert np.all(E == 0.0)
+
+
+@pytest.mark.parametrize("name,cfg", SMALL_CASES)
+def test_residual_parity_small_meshes(name, cfg):
+    p = gprob(cfg)
+    for seed, u in enumerate([inputs.flat_state(p.N, p.M),
+                              inputs.perturbed(inputs.flat_state(p.N, p.M), 1e-3, 1),
+                              inputs.smooth_state(p.N, p.M, 0.05, 2),
+                              inputs.smooth_state(p.N, p.M, 0.2, 3)]):
+        E = gpu_residual(p, u)
+        _check(f"{name}/state{seed}", p, u, E)
+
+
+def test_residual_parity_config2_batch_sampled():
+    """Config 2 (181 x 61), 16 states = linear solution + N(0, 1e-3^2): E1/E4/E6
+    compared everywhere, E2 at 48 sampled collocation points per state (plus the
+    corners of the collocation grid)."""
+    p = gprob(inputs.CONFIG2)
+    op = oprob(p)
+    NM = p.N * p.M
+    rng = np.random.default_rng(123)
+    corners = [NM + 1, NM + p.N - 1, NM + (p.M - 1) * p.N + 1, 2 * NM - 1]
+    worst = 0.0
+    for s, u in enumerate(inputs.config2_batch(16)):
+        E = gpu_residual(p, u)
+        assert np.all(np.isfinite(E))
+        e2 = NM + rng.integers(0, p.M, 48) * p.N + rng.integers(1, p.N, 48)
+        rows = np.unique(np.concatenate([np.arange(NM), np.arange(NM, 2 * NM, p.N),
+                                         e2, corners]))
+        Eo, sc = residual_rows(op, u, rows)
+        err = (np.abs(E[rows] - Eo) / sc).max()
+        worst = max(worst, err)
+        assert err <= TOL64, (s, err)
+    log(f"config2 batch: worst rel err {worst:.3e}")
+
+
+def test_residual_is_deterministic():
+    p = gprob(inputs.CONFIG2)
+    u = dev(inputs.config2_batch(1)[0])
+    a = host(api.residual(p, u))
+    b = host(api.residual(p, u))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,cfg", [("config1", inputs.CONFIG1),
+                                      ("ragged97x13", SMALL_CASES[5][1])])
+def test_fp32_kahan_residual_error_is_small(name, cfg):
+    p = gprob(cfg)
+    u = inputs.smooth_state(p.N, p.M, 0.05, 5)
+    E32 = gpu_residual(p.with_(precision="fp32"), u)
+    op = oprob(p)
+    Eo = oresidual(op, u)
+    err = (np.abs(E32 - Eo) / row_scale(op, u)).max()
+    log(f"{name}: FP32-Kahan max rel err vs FP64 oracle {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_fp32_flat_state_without_source_is_exactly_zero():
+    p = gprob(inputs.CONFIG1, eps=0.0, precision="fp32")
+    E = gpu_residual(p, inputs.flat_state(p.N, p.M))
+    assert np.all(E == 0.0)
+
+
+def test_jvp_matches_oracle_difference_quotient_and_exact_derivative():
+    p = gprob(SMALL_CASES[0][1])
+    op = oprob(p)
+    u = inputs.smooth_state(p.N, p.M, 0.05, 7)
+    z = np.random.default_rng(8).standard_normal(u.size)
+    ud, zd = dev(u), dev(z)
+    Eu = api.residual(p, ud)
+    h = 1e-5
+    J = host(api.jvp(p, ud, Eu, zd, h=h))
+    Jo = jvp_fd(op, u, oresidual(op, u), z, h)
+    sc = row_scale(op, u)
+    assert (np.abs(J - Jo) / sc).max() <= 4 * TOL64 / h
+    ex = jvp_complex(op, u, z)
+    Ja = host(api.jvp(p, ud, Eu, zd, h=0.0))
+    rel = np.abs(Ja - ex).max() / np.abs(ex).max()
+    log(f"jvp auto-h vs exact: {rel:.2e}")
+    assert rel <= 1e-5
+    zero = host(api.jvp(p, ud, Eu, torch.zeros_like(zd), h=0.0))
+    assert np.all(zero == 0.0)
+
+
+def test_zeta_matches_trapezoid_integration():
+    p = gprob(inputs.CONFIG1)
+    u = inputs.smooth_state(p.N, p.M, 0.05, 9)
+    z = host(api.zeta(p, dev(u)))
+    ref = zeta_grid(oprob(p), u).ravel()
+    assert np.abs(z - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_invalid_arguments_are_rejected():
+    p = gprob(inputs.CONFIG1)
+    u = dev(inputs.flat_state(p.N, p.M))
+    with pytest.raises(Exception):
+        api.residual(p.with_(N=3), dev(inputs.flat_state(3, p.M)))
+    with pytest.raises(Exception):
+        api.residual(p.with_(F=0.0), u)
+    with pytest.raises(Exception):
+        api.residual(p.with_(N=30, weights="simpson"), dev(inputs.flat_state(30, p.M)))

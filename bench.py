@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X ship-wave Newton-Krylov path.
+
+One step = one complete FP64 Jacobian-free Newton-Krylov solve of the 181 x 61
+workload (x in [-16, 8], y in [0, 12], eps = 0.1, F = 0.7) from the flat
+surface to ||E||_inf <= 1e-10, including the set-up of the banded
+linear-Jacobian preconditioner (block half-bandwidth q, default 1).  Inputs
+are synthetic (the flat state), device-resident before timing starts.
+
+Printed on one JSON line:
+  value          solves/s over the timed steps (whole job, one GPU)
+  roofline       the all-pairs residual kernel, timed live with HIP events on
+                 its launch stream: 48 algorithmic flops per (collocation,
+                 grid) pair against the FP64 vector peak of the MI355X
+  cpu_baseline   the FP64 CPU oracle on a bounded sample of the same workload
+  extra          residual throughput on the 16-state batch (FP64, FP32-Kahan),
+                 solve with a prebuilt preconditioner, mixed-precision solve,
+                 iteration counts
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 48          # algorithmic flop-equivalents per pair (FMA = 2, rsqrt = 1)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+PAPER_TABLE1_181x61_GPU_S = 0.18   # M2090 function evaluation, eps = 1, F = 0.7 (Table 1)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--q", type=int, default=4, help="preconditioner block half-bandwidth")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, evals_per_solve):
+    """Time the oracle's FP64 residual on config-2 states: the full E(u) of one
+    perturbed linear-solution state, then scale by the residual evaluations one
+    GPU solve needed (Krylov, preconditioner and line-search work are left
+    out, which favours the CPU)."""
+    import numpy as np
+    from oracle import Problem as OProblem
+    from oracle.equations import residual as oresidual
+    from paper_1403_5044_amd import inputs
+    op = OProblem(cfg["N"], cfg["M"], cfg["x1"], cfg["xN"], cfg["yM"], F=cfg["F"], eps=cfg["eps"])
+    u = inputs.config2_batch(1)[0]
+    t0 = time.perf_counter()
+    E = oresidual(op, u)
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(E))
+    pairs = (op.N - 1) * op.M * op.N * op.M
+    per_solve = dt * evals_per_solve
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one full FP64 oracle residual E(u) on 181x61 (numpy, single thread): "
+                       f"{dt:.2f} s = {pairs / dt:.3e} pairs/s; scaled by the {evals_per_solve} "
+                       f"residual evaluations of one GPU solve")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1403_5044_amd import api, inputs
+    from paper_1403_5044_amd import _lib
+    _lib.load()  # fails loudly if the HIP library is not built
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg = inputs.CONFIG2
+    N, M = cfg["N"], cfg["M"]
+    solve_kw = dict(q_blocks=args.q, tol=1e-10)
+
+    def one_solve(**kw):
+        kk = dict(solve_kw)
+        kk.update(kw)
+        return api.solve(cfg["F"], cfg["eps"], N, M, cfg["x1"], cfg["xN"], cfg["yM"], **kk)
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    api.profile_enable(True)
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        _, _, info = one_solve()
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kms, pairs = api.profile_read()
+    api.profile_enable(False)
+    for i, info in enumerate(infos):
+        print(f"step {i}: {info}", file=sys.stderr, flush=True)
+        if info.status != 0:
+            print("solve did not converge", file=sys.stderr)
+            sys.exit(1)
+    dt = t1 - t0
+    value = args.steps / dt
+    avg_ms = kms / max(launches, 1)
+    flops_per_launch = FLOP_PER_PAIR * pairs / max(launches, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_pairs_f64 (all-pairs boundary-integral sum)",
+                "launches": launches, "avg_launch_ms": avg_ms,
+                "flop_per_launch": flops_per_launch}
+    extra = {"newton_iters": infos[-1].newton_iters, "gmres_iters": infos[-1].gmres_iters,
+             "residual_evals": infos[-1].residual_evals,
+             "precond_build_s": infos[-1].time_precond_s,
+             "pair_kernel_share_of_step": kms * 1e-3 / dt}
+    if not args.no_extra:
+        extra.update(extra_measurements(api, inputs, cfg, one_solve))
+    out = {
+        "metric": "JFNK solves/s & pair-interactions/s (frac FP64 peak); p50/p99 solve latency",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"FP64 JFNK solve from the flat surface, mesh {N}x{M}, "
+                                f"x in [{cfg['x1']}, {cfg['xN']}], y in [0, {cfg['yM']}], "
+                                f"eps {cfg['eps']}, F {cfg['F']}, tol 1e-10, preconditioner "
+                                f"q={args.q} built inside each step"),
+                   "unknowns": 2 * N * M, "pairs_per_residual": (N - 1) * M * N * M},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, infos[-1].residual_evals)
+    out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+def extra_measurements(api, inputs, cfg, one_solve):
+    import torch
+    res = {}
+    p = api.Problem(**cfg)
+    batch = [torch.tensor(u, device="cuda") for u in inputs.config2_batch(16)]
+    outs = [torch.empty_like(b) for b in batch]
+    for prec in ("fp64", "fp32"):
+        pp = p.with_(precision=prec)
+        for u, e in zip(batch, outs):
+            api.residual(pp, u, out=e)
+        torch.cuda.synchronize()
+        reps = 3
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            for u, o in zip(batch, outs):
+                api.residual(pp, u, out=o)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / (reps * len(batch))
+        res[f"batch16_{prec}_residual_ms"] = ms
+        res[f"batch16_{prec}_pairs_per_s"] = p.pairs / (ms * 1e-3)
+        res[f"batch16_{prec}_residuals_per_s"] = 1e3 / ms
+    res["paper_table1_181x61_gpu_eval_s"] = PAPER_TABLE1_181x61_GPU_S
+    # solve with a prebuilt preconditioner (reused across solves of one mesh and F)
+    P = api.Preconditioner(p, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = one_solve(precond=P)
+    torch.cuda.synchronize()
+    res["solve_prebuilt_precond_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, infom = one_solve(precond=P, precision="fp32")
+    torch.cuda.synchronize()
+    res["solve_mixed_prebuilt_precond_s"] = time.perf_counter() - t0
+    res["solve_mixed_iters"] = [infom.newton_iters, infom.gmres_iters, infom.residual_evals]
+    P.close()
+    return res
+
+
+if __name__ == "__main__":
+    main()

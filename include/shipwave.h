@@ -100,17 +100,19 @@ const char* shipwave_last_error(void);
  * selects the arithmetic of the all-pairs sum. */
 int32_t shipwave_residual(const sw_problem* prob, const double* u, double* E, hipStream_t stream);
 
-/* E(u) for nb independent problems (each with its own mesh, F, eps, precision),
- * evaluated by shared launches: one prelude launch per kernel over all
- * problems and one all-pairs launch over a combined work list.  probs: host
- * array of nb problems; u, E: host arrays of nb device pointers.  Each
- * result is bitwise identical to shipwave_residual on that problem alone. */
+/* E(u) for nb independent problems (each with its own mesh, F, eps, precision).
+ * The all-pairs sums of all problems of one precision run in one shared launch
+ * over a combined work list (up to 24 problems per launch); the O(NM) prelude
+ * and assembly kernels run per problem.  probs: host array of nb problems;
+ * u, E: host arrays of nb device pointers.  Each result is bitwise identical
+ * to shipwave_residual on that problem alone. */
 int32_t shipwave_residual_batched(int32_t nb, const sw_problem* probs, const double* const* u,
                                   double* const* E, hipStream_t stream);
 
 /* Jacobian-vector product by a first-order difference quotient (eq. JvApprox):
  * Jz = (E(u + h z) - Eu) / h.  Eu must be E(u) computed with the same
- * precision setting.  h <= 0 selects h = sqrt(macheps) (1 + ||u||_2) / ||z||_2
+ * precision setting.  h <= 0 selects h = sqrt(macheps) (sqrt(n) + ||u||_2) / ||z||_2,
+ * n = 2NM, which moves each entry of u by about sqrt(macheps) (1 + rms(u))
  * (macheps of the pair-sum precision).  u, Eu, z, Jz: device, 2NM doubles;
  * Jz may not alias u or z.  A zero z gives Jz = 0. */
 int32_t shipwave_jvp(const sw_problem* prob, const double* u, const double* Eu, const double* z,
@@ -128,7 +130,8 @@ typedef struct sw_precond sw_precond;
 int32_t shipwave_precond_build_banded(const sw_problem* prob, int32_t q_blocks, sw_precond** out,
                                       hipStream_t stream);
 /* x = P^{-1} b by the three-step block solve of Appendix C.  b, x: device,
- * 2NM doubles; may alias. */
+ * 2NM doubles; may alias.  The handle owns the apply's temporaries, so applies
+ * of one handle must not run concurrently on different streams. */
 int32_t shipwave_precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t stream);
 void shipwave_precond_destroy(sw_precond* P);
 
@@ -137,14 +140,15 @@ typedef struct {
     int32_t max_newton;    /* default 50 */
     int32_t gmres_restart; /* Krylov dimension m before restart (default 30) */
     int32_t max_gmres;     /* GMRES iterations per Newton step (default 200) */
-    int32_t q_blocks;      /* preconditioner block half-bandwidth (default 1; <0 -> default) */
+    int32_t q_blocks;      /* preconditioner block half-bandwidth (default 4; <0 -> 1) */
     int32_t precision;     /* SW_PREC_FP64, or SW_PREC_FP32: FP32-Kahan inner JVPs, FP64 outer */
     int32_t weights;       /* SW_WEIGHTS_* */
     int32_t spline_bc;     /* SW_SPLINE_* */
     int32_t init;          /* 0: flat surface initial guess; 1: caller's u_inout */
     double nu;             /* 0 -> 0.05 */
     double eta_max;        /* Eisenstat-Walker forcing cap (default 0.9; <=0 -> default) */
-    const sw_precond* precond; /* optional prebuilt preconditioner for this mesh/F; NULL -> build */
+    const sw_precond* precond; /* optional prebuilt preconditioner for this mesh and domain
+                                  (any F: it only affects convergence speed); NULL -> build */
 } sw_solve_opts;
 
 typedef struct {
@@ -174,6 +178,16 @@ int32_t shipwave_solve(double F, double eps, const sw_mesh* mesh, const sw_domai
 
 /* Surface heights zeta_{k,l} ([l][k], N*M doubles, device) of a state u. */
 int32_t shipwave_zeta(const sw_problem* prob, const double* u, double* zeta, hipStream_t stream);
+
+/* ---- diagnostics ----------------------------------------------------------
+ * Times every all-pairs kernel launch (the dominant kernel of E(u)) with a
+ * pair of HIP events recorded on the launch stream around it.
+ * shipwave_profile_enable(1) clears the record and starts recording,
+ * enable(0) stops.  shipwave_profile_read waits for the recorded events and
+ * returns the number of launches, their summed duration in milliseconds and
+ * the summed number of (collocation, grid) pairs they evaluated. */
+int32_t shipwave_profile_enable(int32_t on);
+int32_t shipwave_profile_read(int64_t* launches, double* total_ms, double* pairs);
 
 /* ---- serving: continuous batching of many solves on one GPU ------------ */
 typedef struct sw_server sw_server;

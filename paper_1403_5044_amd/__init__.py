@@ -5,5 +5,5 @@ patterns (flow past a submerged source): HIP kernels behind a C ABI
 The library (libshipwave.so) is loaded on first use; nothing here computes
 the method on the CPU.
 """
-from .api import (Preconditioner, Problem, SolveInfo, jvp, residual,  # noqa: F401
+from .api import (Preconditioner, Problem, Server, SolveInfo, jvp, residual,  # noqa: F401
                   residual_batched, solve, zeta)

@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libshipwave.so")
+LIB_PATH = os.environ.get("SHIPWAVE_LIB") or os.path.join(HERE, "libshipwave.so")
 
 
 class SwMesh(C.Structure):
@@ -78,6 +78,8 @@ SIGNATURES = {
     "shipwave_solve": (I32, [D, D, C.POINTER(SwMesh), C.POINTER(SwDomain),
                              C.POINTER(SwSolveOpts), P, P, C.POINTER(SwSolveInfo), P]),
     "shipwave_zeta": (I32, [C.POINTER(SwProblem), P, P, P]),
+    "shipwave_profile_enable": (I32, [I32]),
+    "shipwave_profile_read": (I32, [C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]),
     "shipwave_server_create": (I32, [C.POINTER(SwServerOpts), C.POINTER(P)]),
     "shipwave_server_submit": (I32, [P, C.POINTER(SwRequest), C.POINTER(C.c_uint64)]),
     "shipwave_server_poll": (I32, [P, C.c_uint64, C.POINTER(SwResult), P]),

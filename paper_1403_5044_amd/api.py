@@ -121,6 +121,20 @@ def zeta(prob: Problem, u, out=None):
     return out
 
 
+def profile_enable(on: bool = True):
+    """Start (clear) or stop event timing of the all-pairs kernel launches."""
+    L.check(_lib().shipwave_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(launches, total kernel milliseconds, total pairs) since profile_enable(True)."""
+    n = C.c_int64()
+    ms = C.c_double()
+    pr = C.c_double()
+    L.check(_lib().shipwave_profile_read(C.byref(n), C.byref(ms), C.byref(pr)))
+    return n.value, ms.value, pr.value
+
+
 class Preconditioner:
     """Linear-Jacobian block preconditioner with block half-bandwidth q."""
 
@@ -206,3 +220,75 @@ def solve(F: float, eps: float, N: int, M: int, x1: float, xN: float, yM: float,
     if check and rc not in (0, -4):
         L.check(rc)
     return u, z, si
+
+
+@dataclass
+class Result:
+    status: int
+    newton_iters: int
+    gmres_iters: int
+    residual_evals: int
+    used_fallback: int
+    final_norm: float
+    t_submit_s: float
+    t_admit_s: float
+    t_done_s: float
+    zeta: object = None
+
+
+class Server:
+    """Continuous-batching solve server (one worker thread and stream on the GPU)."""
+
+    def __init__(self, hbm_budget_bytes: float = 8e9, max_slots: int = 16,
+                 precision: str = "fp32", fallback_fp64: bool = True, tol: float = 1e-10,
+                 q_blocks: int = 4):
+        self.lib = _lib()
+        o = L.SwServerOpts()
+        o.hbm_budget_bytes = float(hbm_budget_bytes)
+        o.max_slots = int(max_slots)
+        o.fallback_fp64 = 1 if fallback_fp64 else 0
+        o.tol = float(tol)
+        o.q_blocks = int(q_blocks)
+        o.precision = PRECISION[precision]
+        h = C.c_void_p()
+        L.check(self.lib.shipwave_server_create(C.byref(o), C.byref(h)))
+        self.handle = h
+        self.meshes = {}
+
+    def submit(self, F, eps, N, M, x1, xN, yM) -> int:
+        r = L.SwRequest()
+        r.mesh.N, r.mesh.M = N, M
+        r.domain.x1, r.domain.xN, r.domain.yM = x1, xN, yM
+        r.F, r.eps = F, eps
+        t = C.c_uint64()
+        L.check(self.lib.shipwave_server_submit(self.handle, C.byref(r), C.byref(t)))
+        self.meshes[t.value] = N * M
+        return t.value
+
+    def poll(self, ticket: int):
+        """Result (with zeta as a numpy array) or None while pending."""
+        import numpy as np
+        res = L.SwResult()
+        z = np.empty(self.meshes[ticket], dtype=np.float64)
+        rc = self.lib.shipwave_server_poll(self.handle, C.c_uint64(ticket), C.byref(res),
+                                           z.ctypes.data_as(C.c_void_p))
+        if rc == -6:
+            return None
+        L.check(rc)
+        return Result(res.status, res.newton_iters, res.gmres_iters, res.residual_evals,
+                      res.used_fallback, res.final_norm, res.t_submit_s, res.t_admit_s,
+                      res.t_done_s, z)
+
+    def drain(self):
+        L.check(self.lib.shipwave_server_drain(self.handle))
+
+    def close(self):
+        if self.handle:
+            self.lib.shipwave_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

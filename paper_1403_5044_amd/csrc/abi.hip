@@ -94,42 +94,45 @@ Scratch& scratch_for(hipStream_t stream, int slot) {
     return *p;
 }
 
+// ---- diagnostics: event timing of the all-pairs launches -------------------------
 namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+struct ProfRec {
+    hipEvent_t a, b;
+    double pairs;
+};
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
 
-__global__ void k_jvp_h(const double* norms_u, const double* norms_z, double sqrt_eps,
-                        double* h) {
-    // norms_*[1] = 2-norm; h[0] = step, h[1] = 1/step (0 if z == 0)
-    const double nz = norms_z[1];
-    if (nz > 0.0) {
-        const double s = sqrt_eps * (1.0 + norms_u[1]) / nz;
-        h[0] = s;
-        h[1] = 1.0 / s;
-    } else {
-        h[0] = 0.0;
-        h[1] = 0.0;
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
     }
+    hipEvent_t e = nullptr;
+    SW_HIP(hipEventCreate(&e));
+    return e;
 }
-
-__global__ void k_set_h(double h, double* out) {
-    out[0] = h;
-    out[1] = 1.0 / h;
-}
-
-__global__ void k_shift(int n, const double* __restrict__ u, const double* __restrict__ z,
-                        const double* __restrict__ h, double* __restrict__ out) {
-    const double s = h[0];
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-        out[t] = fma(s, z[t], u[t]);
-}
-
-__global__ void k_quot(int n, const double* __restrict__ Ep, const double* __restrict__ Eu,
-                       const double* __restrict__ h, double* __restrict__ out) {
-    const double r = h[1];
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-        out[t] = (Ep[t] - Eu[t]) * r;
-}
-
 }  // namespace
+
+ProfileMark profile_begin(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfileMark m;
+    if (!g_prof_on) return m;
+    m.a = prof_event();
+    m.b = prof_event();
+    SW_HIP(hipEventRecord(m.a, s));
+    return m;
+}
+
+void profile_end(const ProfileMark& m, hipStream_t s, double pairs) {
+    if (!m.a) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    SW_HIP(hipEventRecord(m.b, s));
+    g_prof.push_back(ProfRec{m.a, m.b, pairs});
+}
 
 void residual_one(const Geo& g, const double* u, double* E, hipStream_t s) {
     const int G = choose_chunks(g);
@@ -144,7 +147,7 @@ void jvp_one(const Geo& g, const double* u, const double* Eu, const double* z, d
              double* Jz, hipStream_t s) {
     const int n = 2 * g.NM;
     Scratch& sc = scratch_for(s, 1);
-    const size_t wd = reduce_work_doubles(n);
+    const size_t wd = reduce_work_doubles(n, 2);
     sc.ensure(carve_size({(size_t)n * 8, (size_t)n * 8, 64, 64, 64, wd * 8}));
     Carve c(sc.base);
     double* up = c.take<double>(n);
@@ -154,17 +157,17 @@ void jvp_one(const Geo& g, const double* u, const double* Eu, const double* z, d
     double* nz_ = c.take<double>(2);
     double* work = c.take<double>(wd);
     if (h > 0.0) {
-        k_set_h<<<1, 1, 0, s>>>(h, hd);
+        set_step(h, hd, s);
     } else {
         const double macheps = (g.precision == SW_PREC_FP32) ? 1.1920928955078125e-07
                                                               : 2.220446049250313e-16;
         norm_inf_2(n, u, nu_, work, s);
         norm_inf_2(n, z, nz_, work, s);
-        k_jvp_h<<<1, 1, 0, s>>>(nu_, nz_, std::sqrt(macheps), hd);
+        jvp_step(nu_, nz_, std::sqrt(macheps), std::sqrt((double)n), hd, s);
     }
-    k_shift<<<(n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096, 256, 0, s>>>(n, u, z, hd, up);
+    shift(n, u, z, hd, up, s);
     residual_one(g, up, Ep, s);
-    k_quot<<<(n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096, 256, 0, s>>>(n, Ep, Eu, hd, Jz);
+    quotient(n, Ep, Eu, hd, Jz, s);
     SW_HIP(hipGetLastError());
 }
 
@@ -188,6 +191,22 @@ int32_t shipwave_residual(const sw_problem* prob, const double* u, double* E, hi
     });
 }
 
+int32_t shipwave_residual_batched(int32_t nb, const sw_problem* probs, const double* const* u,
+                                  double* const* E, hipStream_t stream) {
+    return guard([&]() -> int32_t {
+        SW_REQUIRE(nb >= 0, "nb must be >= 0");
+        if (nb == 0) return SW_OK;
+        SW_REQUIRE(probs && u && E, "null pointer");
+        std::vector<Geo> g(nb);
+        for (int i = 0; i < nb; ++i) {
+            g[i] = make_geo(probs[i]);
+            SW_REQUIRE(u[i] && E[i], "null pointer");
+        }
+        residual_batched_enqueue(nb, g.data(), u, E, stream);
+        return SW_OK;
+    });
+}
+
 int32_t shipwave_jvp(const sw_problem* prob, const double* u, const double* Eu, const double* z,
                      double h, double* Jz, hipStream_t stream) {
     return guard([&]() -> int32_t {
@@ -196,6 +215,39 @@ int32_t shipwave_jvp(const sw_problem* prob, const double* u, const double* Eu, 
         const Geo g = make_geo(*prob);
         SW_REQUIRE(Jz != u && Jz != z, "Jz may not alias u or z");
         jvp_one(g, u, Eu, z, h, Jz, stream);
+        return SW_OK;
+    });
+}
+
+int32_t shipwave_profile_enable(int32_t on) {
+    return guard([&]() -> int32_t {
+        std::lock_guard<std::mutex> lk(sw::g_prof_mu);
+        for (auto& r : sw::g_prof) {
+            (void)hipEventSynchronize(r.b);
+            sw::g_prof_pool.push_back(r.a);
+            sw::g_prof_pool.push_back(r.b);
+        }
+        sw::g_prof.clear();
+        sw::g_prof_on = (on != 0);
+        return SW_OK;
+    });
+}
+
+int32_t shipwave_profile_read(int64_t* launches, double* total_ms, double* pairs) {
+    return guard([&]() -> int32_t {
+        SW_REQUIRE(launches && total_ms && pairs, "null pointer");
+        std::lock_guard<std::mutex> lk(sw::g_prof_mu);
+        double ms = 0.0, pr = 0.0;
+        for (auto& r : sw::g_prof) {
+            SW_HIP(hipEventSynchronize(r.b));
+            float t = 0.0f;
+            SW_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            ms += t;
+            pr += r.pairs;
+        }
+        *launches = (int64_t)sw::g_prof.size();
+        *total_ms = ms;
+        *pairs = pr;
         return SW_OK;
     });
 }

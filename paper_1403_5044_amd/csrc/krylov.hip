@@ -124,6 +124,49 @@ __global__ void k_norm2(int B, const double* __restrict__ work, double* __restri
     out2[1] = sqrt(s);
 }
 
+__global__ void k_jvp_h(const double* norms_u, const double* norms_z, double sqrt_eps,
+                        double sqrt_n, double* h) {
+    // h[0] = step, h[1] = 1/step (both 0 if z == 0); the step moves each entry of u by
+    // about sqrt(macheps) (1 + rms(u)).
+    const double nz = norms_z[1];
+    if (nz > 0.0) {
+        const double st = sqrt_eps * (sqrt_n + norms_u[1]) / nz;
+        h[0] = st;
+        h[1] = 1.0 / st;
+    } else {
+        h[0] = 0.0;
+        h[1] = 0.0;
+    }
+}
+
+__global__ void k_set_h(double h, double* out) {
+    out[0] = h;
+    out[1] = 1.0 / h;
+}
+
+__global__ __launch_bounds__(kThreads) void k_shift(int n, const double* __restrict__ u,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ h,
+                                                    double* __restrict__ out) {
+    const double st = h[0];
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        out[t] = fma(st, z[t], u[t]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_quot(int n, const double* __restrict__ Ep,
+                                                   const double* __restrict__ Eu,
+                                                   const double* __restrict__ h,
+                                                   double* __restrict__ out) {
+    const double r = h[1];
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        out[t] = (Ep[t] - Eu[t]) * r;
+}
+
+__global__ void k_flat(int NM, double* u) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * NM; t += gridDim.x * blockDim.x)
+        u[t] = (t < NM) ? 1.0 : 0.0;
+}
+
 inline int ew_blocks(int n) {
     int b = (n + kThreads - 1) / kThreads;
     return b < 1 ? 1 : (b > 4096 ? 4096 : b);
@@ -131,7 +174,7 @@ inline int ew_blocks(int n) {
 
 }  // namespace
 
-size_t reduce_work_doubles(int n) { return (size_t)64 * red_blocks(n) + 64; }
+size_t reduce_work_doubles(int n, int k) { return (size_t)(k + 2) * red_blocks(n) + 64; }
 
 void axpby(int n, double a, const double* x, double b, const double* y, double* out,
            hipStream_t s) {
@@ -164,5 +207,24 @@ void norm_inf_2(int n, const double* x, double* out2, double* work, hipStream_t 
     k_norm1<<<B, kThreads, 0, s>>>(n, x, work);
     k_norm2<<<1, 64, 0, s>>>(B, work, out2);
 }
+
+void jvp_step(const double* norms_u, const double* norms_z, double sqrt_eps, double sqrt_n,
+              double* h, hipStream_t s) {
+    k_jvp_h<<<1, 1, 0, s>>>(norms_u, norms_z, sqrt_eps, sqrt_n, h);
+}
+
+void set_step(double h, double* out, hipStream_t s) { k_set_h<<<1, 1, 0, s>>>(h, out); }
+
+void shift(int n, const double* u, const double* z, const double* h, double* out,
+           hipStream_t s) {
+    k_shift<<<ew_blocks(n), kThreads, 0, s>>>(n, u, z, h, out);
+}
+
+void quotient(int n, const double* Ep, const double* Eu, const double* h, double* out,
+              hipStream_t s) {
+    k_quot<<<ew_blocks(n), kThreads, 0, s>>>(n, Ep, Eu, h, out);
+}
+
+void flat_state(int NM, double* u, hipStream_t s) { k_flat<<<256, 256, 0, s>>>(NM, u); }
 
 }  // namespace sw

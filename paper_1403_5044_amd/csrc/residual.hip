@@ -19,34 +19,21 @@
 // (every lane reads the same record: an LDS broadcast).  The per-row terms
 // (y offsets and their products with B, C) are hoisted out of the source loop.
 #include "sw_internal.hpp"
+#include "sw_device.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 namespace sw {
 
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip.  Map the
-// hardware block id to a work id such that each XCD receives a contiguous
-// range of work ids (and hence a contiguous range of source chunks, which then
-// share that XCD's L2).  Bijective on [0, nblocks).
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-    constexpr int kXcd = 8;
-    const int xcd = b % kXcd;
-    const int idx = b / kXcd;
-    const int base = nblocks / kXcd;
-    const int rem = nblocks % kXcd;
-    return xcd * base + min(xcd, rem) + idx;
-}
-
-__device__ __forceinline__ double weight1d(int i, int n, int rule) {
-    if (rule == SW_WEIGHTS_TRAPEZOID) return (i == 0 || i == n - 1) ? 0.5 : 1.0;
-    if (i == 0 || i == n - 1) return 1.0 / 3.0;
-    return (i & 1) ? 4.0 / 3.0 : 2.0 / 3.0;
-}
+constexpr int kMaxDenseSplineM = 512;
 
 // ---- a1-a2: trapezoid integration in x, radiation rows -------------------------
 // One wavefront per (row l, field f): f = 0 -> psi from phi_x - 1, f = 1 -> zeta.
@@ -156,36 +143,61 @@ __global__ __launch_bounds__(128) void k_spline(Geo g, const double* __restrict_
     }
 }
 
-// ---- a4: closed form of I -----------------------------------------------------------
-// L(P,B,R;t) = int_0^t ds / sqrt(P s^2 + B s + R) = P^{-1/2} ln((2 sqrt(P) q(t) + 2Pt + B) /
-// (2 sqrt(PR) + B)), q(t) = sqrt(P t^2 + B t + R); a negative 2Pt + B (or B) is
-// handled through the conjugate (4PR - B^2) / (2 sqrt(P) q - 2Pt - B).
-__device__ double lint(double P, double B, double R, double disc, double t) {
-    const double sP = sqrt(P);
-    const double q = sqrt(fma(fma(P, t, B), t, R));
-    const double lin = fma(2.0 * P, t, B);
-    const double top = (lin >= 0.0) ? fma(2.0 * sP, q, lin) : disc / fma(2.0 * sP, q, -lin);
-    const double s0 = 2.0 * sqrt(P * R);
-    const double bot = (B >= 0.0) ? s0 + B : disc / (s0 - B);
-    return log(top / bot) / sP;
+// Slope operator of the spline for h = 1: slopes = (1/h) Q f, one column of Q per
+// thread (the slopes of the unit vector e_m), same elimination as k_spline.
+__global__ void k_spline_operator(int M, int bc, double* __restrict__ Q) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    auto f = [m](int j) { return (j == m) ? 1.0 : 0.0; };
+    double* S = Q + m;  // column m, stride M
+    double cp = (bc == SW_SPLINE_CLAMPED0) ? 0.0 : 2.0;
+    double d0 = (bc == SW_SPLINE_CLAMPED0) ? 0.0 : 0.5 * (5.0 * (f(1) - f(0)) + (f(2) - f(1)));
+    double dp = d0;
+    S[0] = dp;
+    double* cps = nullptr;  // cp_j is recomputed on the way back
+    (void)cps;
+    for (int j = 1; j < M - 1; ++j) {
+        const double mj = 4.0 - cp;
+        dp = (3.0 * (f(j + 1) - f(j - 1)) - dp) / mj;
+        cp = 1.0 / mj;
+        S[(size_t)j * M] = dp;
+    }
+    {
+        const double mj = 1.0 - 2.0 * cp;
+        const double dl = 0.5 * ((f(M - 2) - f(M - 3)) + 5.0 * (f(M - 1) - f(M - 2)));
+        dp = (dl - 2.0 * dp) / mj;
+    }
+    S[(size_t)(M - 1) * M] = dp;
+    // back substitution needs cp_j: rebuild the forward sequence into a local recurrence
+    double s = dp;
+    for (int j = M - 2; j >= 0; --j) {
+        double c = (bc == SW_SPLINE_CLAMPED0) ? 0.0 : 2.0;
+        for (int i = 1; i <= j; ++i) c = 1.0 / (4.0 - c);
+        s = S[(size_t)j * M] - c * s;
+        S[(size_t)j * M] = s;
+    }
 }
 
-// G(a,b) = int_0^a int_0^b dY dX / sqrt(A X^2 + B X Y + C Y^2): the rectangle split on
-// its diagonal, Y = tX below and X = sY above.
-__device__ double grect(double A, double B, double C, double disc, double a, double b) {
-    if (!(a > 0.0) || !(b > 0.0)) return 0.0;
-    return a * lint(C, B, A, disc, b / a) + b * lint(A, B, C, disc, a / b);
-}
-
-__device__ double closed_form_I(double A, double B, double C, double disc, double a1, double a2,
-                                double ys, double yM) {
-    const double b1 = ys, b2 = yM - ys;
-    const double direct = grect(A, B, C, disc, a2, b2) + grect(A, -B, C, disc, a1, b2) +
-                          grect(A, -B, C, disc, a2, b1) + grect(A, B, C, disc, a1, b1);
-    const double yt = yM + ys;
-    const double image = (grect(A, -B, C, disc, a2, yt) + grect(A, B, C, disc, a1, yt)) -
-                         (grect(A, -B, C, disc, a2, ys) + grect(A, B, C, disc, a1, ys));
-    return direct + image;
+// psi_y, zeta_y = (1/h) Q f for every column at once: block (x-tile, row j, field).
+__global__ __launch_bounds__(128) void k_spline_dense(Geo g, const double* __restrict__ Q,
+                                                      const double* __restrict__ psi,
+                                                      const double* __restrict__ zeta,
+                                                      double* __restrict__ psiy,
+                                                      double* __restrict__ zetay) {
+    const int k = blockIdx.x * 128 + threadIdx.x;
+    const int j = blockIdx.y;
+    const int f = blockIdx.z;
+    if (k >= g.N) return;
+    const double* F = (f == 0 ? psi : zeta) + k;
+    const double* q = Q + (size_t)j * g.M;
+    double s0 = 0.0, s1 = 0.0;
+    int m = 0;
+    for (; m + 1 < g.M; m += 2) {
+        s0 = fma(q[m], F[(size_t)m * g.N], s0);
+        s1 = fma(q[m + 1], F[(size_t)(m + 1) * g.N], s1);
+    }
+    if (m < g.M) s0 = fma(q[m], F[(size_t)m * g.N], s0);
+    (f == 0 ? psiy : zetay)[(size_t)j * g.N + k] = (s0 + s1) / g.dy;
 }
 
 // Source record (64 B): x, zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
@@ -462,14 +474,68 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(Geo g, const float* 
     pairs_f32_body<CP>(g, src, col, partial, w % ntiles, w / ntiles, G, ldsf);
 }
 
+// Batched all-pairs launch: a work list of (problem, collocation tile, source
+// chunk) items over several problems, each problem with its own geometry and
+// buffers.  Every item runs the same body as the single-problem launch with
+// the same tile/chunk split, so each problem's partial sums are bitwise those
+// of its own launch.
+struct PairProb {
+    Geo g;
+    const void* src;
+    const double* col;
+    double* partial;
+    int ntiles;
+    int G;
+    int first_block;  // first work-list index of this problem
+    int pad;
+};
+constexpr int kMaxBatch = 24;  // keeps the kernel argument block under 4 KB
+struct PairBatch {
+    PairProb p[kMaxBatch];
+    int nprob;
+    int total;
+};
+
+template <int CP>
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f64_batched(PairBatch b) {
+    extern __shared__ double lds[];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    int q = 0;
+    while (q + 1 < b.nprob && w >= b.p[q + 1].first_block) ++q;
+    const PairProb& pp = b.p[q];
+    const int local = w - pp.first_block;
+    pairs_f64_body<CP>(pp.g, static_cast<const double*>(pp.src), pp.col, pp.partial,
+                       local % pp.ntiles, local / pp.ntiles, pp.G, lds);
+}
+
+template <int CP>
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f32_batched(PairBatch b) {
+    extern __shared__ float ldsf[];
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    int q = 0;
+    while (q + 1 < b.nprob && w >= b.p[q + 1].first_block) ++q;
+    const PairProb& pp = b.p[q];
+    const int local = w - pp.first_block;
+    pairs_f32_body<CP>(pp.g, static_cast<const float*>(pp.src), pp.col, pp.partial,
+                       local % pp.ntiles, local / pp.ntiles, pp.G, ldsf);
+}
+
 // ---- a6: E2 assembly ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict__ col,
                                                 const double* __restrict__ partial, int G,
                                                 double* __restrict__ E) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncol) return;
-    double s = 0.0;
-    for (int q = 0; q < G; ++q) s += partial[(size_t)q * g.ncol + c];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 3 < G; q += 4) {
+        s0 += partial[(size_t)q * g.ncol + c];
+        s1 += partial[(size_t)(q + 1) * g.ncol + c];
+        s2 += partial[(size_t)(q + 2) * g.ncol + c];
+        s3 += partial[(size_t)(q + 3) * g.ncol + c];
+    }
+    for (; q < G; ++q) s0 += partial[(size_t)q * g.ncol + c];
+    const double s = (s0 + s1) + (s2 + s3);
     const int l = c / g.Nc;
     const int k = c - l * g.Nc;
     E[(size_t)g.NM + (size_t)l * g.N + k + 1] = col[(size_t)c * 8 + 6] - s;
@@ -489,15 +555,49 @@ __global__ __launch_bounds__(64) void k_zeta_rows(Geo g, const double* __restric
     }
 }
 
-constexpr int kCP64 = 2;
-constexpr int kCP32 = 2;
+// Collocation points per lane (register blocking of the pair loop).
+#ifndef SW_CP64
+#define SW_CP64 2
+#endif
+#ifndef SW_CP32
+#define SW_CP32 2
+#endif
+constexpr int kCP64 = SW_CP64;
+constexpr int kCP32 = SW_CP32;
 
 }  // namespace
+
+// Dense spline slope operators, cached per (device, M, end condition); NULL for
+// M above kMaxDenseSplineM (then the tridiagonal sweep per column is used).
+const double* spline_operator(int M, int bc, hipStream_t s) {
+    if (M > kMaxDenseSplineM) return nullptr;
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, double*> cache;
+    int dev = -1;
+    SW_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_tuple(dev, M, bc);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    double* Q = nullptr;
+    if (hipMalloc(&Q, (size_t)M * M * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{SW_ENOMEM, "device allocation of the spline operator failed"};
+    }
+    k_spline_operator<<<(M + 63) / 64, 64, 0, s>>>(M, bc, Q);
+    SW_HIP(hipGetLastError());
+    SW_HIP(hipStreamSynchronize(s));  // other streams may read it right away
+    cache[key] = Q;
+    return Q;
+}
 
 int choose_chunks(const Geo& g) {
     const int cp = (g.precision == SW_PREC_FP32) ? kCP32 : kCP64;
     const int ntiles = (g.ncol + kPairThreads * cp - 1) / (kPairThreads * cp);
-    const int target = 4096;
+#ifndef SW_PAIR_BLOCKS
+#define SW_PAIR_BLOCKS 4096
+#endif
+    const int target = SW_PAIR_BLOCKS;
     int G = (target + ntiles - 1) / ntiles;
     return std::max(1, std::min(G, g.M));
 }
@@ -525,13 +625,14 @@ ResidualBufs carve_residual(Carve& c, const Geo& g, int G) {
     return b;
 }
 
+namespace {
+void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s);
+}
+
 void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBufs& b,
                       hipStream_t s) {
-    k_scan<<<dim3(g.M, 2), 64, 0, s>>>(g, u, b.psi, b.zeta, E);
-    k_spline_setup<<<1, 1, 0, s>>>(g.M, g.bc, b.spl);
-    k_spline<<<(2 * g.N + 127) / 128, 128, 0, s>>>(g, b.spl, b.psi, b.zeta, b.psiy, b.zetay);
-    k_points<<<(g.NM + 255) / 256, 256, 0, s>>>(g, u, b.psi, b.zeta, b.psiy, b.zetay, b.src64,
-                                                 b.src32, b.col, E);
+    prelude(g, u, E, b, s);
+    const ProfileMark pm = profile_begin(s);
     if (g.precision == SW_PREC_FP32) {
         const int ntiles = (g.ncol + kPairThreads * kCP32 - 1) / (kPairThreads * kCP32);
         k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)g.N * 32, s>>>(
@@ -541,7 +642,81 @@ void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBu
         k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)g.N * 64, s>>>(
             g, b.src64, b.col, b.partial, ntiles, b.G);
     }
+    profile_end(pm, s, (double)g.ncol * (double)g.NM);
     k_finish<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, b.col, b.partial, b.G, E);
+    SW_HIP(hipGetLastError());
+}
+
+namespace {
+void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s) {
+    k_scan<<<dim3(g.M, 2), 64, 0, s>>>(g, u, b.psi, b.zeta, E);
+    if (const double* Q = spline_operator(g.M, g.bc, s)) {
+        k_spline_dense<<<dim3((g.N + 127) / 128, g.M, 2), 128, 0, s>>>(g, Q, b.psi, b.zeta,
+                                                                       b.psiy, b.zetay);
+    } else {
+        k_spline_setup<<<1, 1, 0, s>>>(g.M, g.bc, b.spl);
+        k_spline<<<(2 * g.N + 127) / 128, 128, 0, s>>>(g, b.spl, b.psi, b.zeta, b.psiy, b.zetay);
+    }
+    k_points<<<(g.NM + 255) / 256, 256, 0, s>>>(g, u, b.psi, b.zeta, b.psiy, b.zetay, b.src64,
+                                                 b.src32, b.col, E);
+}
+}  // namespace
+
+void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, double* const* E,
+                              hipStream_t s) {
+    // scratch for all problems
+    std::vector<int> G(nb);
+    std::vector<size_t> off(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+        G[i] = choose_chunks(g[i]);
+        off[i + 1] = off[i] + residual_scratch_bytes(g[i], G[i]);
+    }
+    Scratch& sc = scratch_for(s, 3);
+    sc.ensure(off[nb] + 256);
+    std::vector<ResidualBufs> bufs(nb);
+    for (int i = 0; i < nb; ++i) {
+        Carve c(static_cast<char*>(sc.base) + off[i]);
+        bufs[i] = carve_residual(c, g[i], G[i]);
+        prelude(g[i], u[i], E[i], bufs[i], s);
+    }
+    const ProfileMark pm = profile_begin(s);
+    double pairs = 0.0;
+    for (int prec = 0; prec < 2; ++prec) {
+        const int cp = (prec == SW_PREC_FP32) ? kCP32 : kCP64;
+        PairBatch batch{};
+        int maxN = 0;
+        auto flush = [&]() {
+            if (batch.nprob == 0) return;
+            const size_t lds = (size_t)maxN * (prec == SW_PREC_FP32 ? 32 : 64);
+            if (prec == SW_PREC_FP32)
+                k_pairs_f32_batched<kCP32><<<batch.total, kPairThreads, lds, s>>>(batch);
+            else
+                k_pairs_f64_batched<kCP64><<<batch.total, kPairThreads, lds, s>>>(batch);
+            batch = PairBatch{};
+            maxN = 0;
+        };
+        for (int i = 0; i < nb; ++i) {
+            if (g[i].precision != prec) continue;
+            if (batch.nprob == kMaxBatch) flush();
+            PairProb& pp = batch.p[batch.nprob++];
+            pp.g = g[i];
+            pp.src = (prec == SW_PREC_FP32) ? static_cast<const void*>(bufs[i].src32)
+                                             : static_cast<const void*>(bufs[i].src64);
+            pp.col = bufs[i].col;
+            pp.partial = bufs[i].partial;
+            pp.ntiles = (g[i].ncol + kPairThreads * cp - 1) / (kPairThreads * cp);
+            pp.G = G[i];
+            pp.first_block = batch.total;
+            batch.total += pp.ntiles * pp.G;
+            maxN = std::max(maxN, g[i].N);
+            pairs += (double)g[i].ncol * (double)g[i].NM;
+        }
+        flush();
+    }
+    profile_end(pm, s, pairs);
+    for (int i = 0; i < nb; ++i)
+        k_finish<<<(g[i].ncol + 255) / 256, 256, 0, s>>>(g[i], bufs[i].col, bufs[i].partial,
+                                                        G[i], E[i]);
     SW_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,94 @@
+// A Newton-Krylov solve written as a state machine whose every residual
+// evaluation is an explicit request.  A driver calls, per step,
+//   pre(s)   enqueue the device work that produces the next state to evaluate
+//            (req_x) and names the output (req_E) and the precision (req_g);
+//   <evaluate E(req_x) -> req_E, alone or batched with other tasks>;
+//   post(s)  enqueue the device work that consumes req_E and copies the
+//            scalars the host needs into pinned memory;
+//   <synchronise the stream>;
+//   host(s)  read those scalars and advance (Givens rotations, convergence
+//            tests, line-search decisions), possibly enqueueing device work.
+// shipwave_solve drives one task; the server drives many, with one shared
+// residual launch and one stream synchronisation per step for all of them.
+#pragma once
+
+#include <vector>
+
+#include "sw_internal.hpp"
+
+namespace sw {
+
+sw_precond* precond_build(const Geo& g, int q, hipStream_t s);
+void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t s);
+void precond_destroy(sw_precond* P);
+size_t precond_bytes(const sw_precond* P);
+size_t precond_bytes_estimate(const Geo& g, int q);
+bool precond_matches(const sw_precond* P, const Geo& g);
+
+struct SolveParams {
+    double tol = 1e-10;
+    int max_newton = 50;
+    int m = 30;          // GMRES restart length
+    int max_gmres = 200; // Krylov iterations per Newton step
+    int precision = SW_PREC_FP64;
+    double eta_max = 0.9;
+    bool init_flat = true;
+};
+
+class SolveTask {
+   public:
+    // u: device state (2NM doubles, initial guess unless init_flat); dev_mem:
+    // device_bytes(g, m) bytes; pin: pinned_doubles(m) doubles of pinned host memory.
+    SolveTask(const Geo& g64, const SolveParams& prm, const sw_precond* P, double* u,
+              void* dev_mem, double* pin);
+    static size_t device_bytes(const Geo& g, int m);
+    static size_t pinned_doubles(int m);
+
+    bool done() const { return ph_ == Phase::Done; }
+    void pre(hipStream_t s);
+    void post(hipStream_t s);
+    void host(hipStream_t s);
+
+    const double* req_x = nullptr;
+    double* req_E = nullptr;
+    const Geo* req_g = nullptr;
+
+    int status = SW_ENOCONV;
+    int newton = 0;
+    int gmres_total = 0;
+    int evals = 0;
+    double final_norm = 0.0;
+    double* u() const { return u_; }
+    const Geo& geo() const { return g64_; }
+
+   private:
+    enum class Phase { E0, Ein, Krylov, Restart, Line, Done };
+    void newton_top(hipStream_t s);
+    void start_gmres(hipStream_t s);
+    void finish_cycle(hipStream_t s, bool converged);
+    void finish(int st);
+
+    Geo g64_, gin_;
+    SolveParams prm_;
+    const sw_precond* P_;
+    int n_, m_;
+    double sqrt_eps_in_, sqrt_n_;
+    double *u_, *V_, *E_, *Et_, *E32_, *Ejv_, *du_, *ut_, *xs_, *z_, *w_, *hd_, *red_;
+    double *pin_out_, *pin_y_;
+    const double* Ein_ = nullptr;
+    Phase ph_ = Phase::E0;
+    // Newton state
+    double nr_[2] = {0, 0};
+    double prev2_ = 0.0, eta_ = 0.1, lam_ = 1.0;
+    // GMRES state
+    std::vector<double> H_, cs_, sn_, gv_, y_;
+    int j_ = 0, its_ = 0;
+    double beta_ = 0.0, target_ = 0.0, pending_scale_ = 0.0;
+    bool first_cycle_ = true, restart_mode_ = false;
+};
+
+// Pinned host blocks for task scalars, reused across tasks.
+double* pinned_get(size_t doubles);
+void pinned_put(double* p, size_t doubles);
+
+}  // namespace sw

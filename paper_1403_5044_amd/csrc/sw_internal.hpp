@@ -136,7 +136,25 @@ void gemv_acc(int n, int k, const double* V, size_t ldv, const double* y, double
               hipStream_t s);  // out = sum_i y[i] V_i (y on device)
 void norm_inf_2(int n, const double* x, double* out2, double* work,
                 hipStream_t s);  // out2[0] = max|x|, out2[1] = ||x||_2
-size_t reduce_work_doubles(int n);
+// Difference-quotient JVP pieces: h = [step, 1/step] computed on the device from
+// the 2-norms in norms_u[1], norms_z[1]; out = u + step z; out = (Ep - Eu) / step.
+void jvp_step(const double* norms_u, const double* norms_z, double sqrt_eps, double sqrt_n,
+              double* h, hipStream_t s);
+void set_step(double h, double* out, hipStream_t s);
+void shift(int n, const double* u, const double* z, const double* h, double* out, hipStream_t s);
+void quotient(int n, const double* Ep, const double* Eu, const double* h, double* out,
+              hipStream_t s);
+void flat_state(int NM, double* u, hipStream_t s);  // phi_x = 1, zeta_x = 0
+void residual_one(const Geo& g, const double* u, double* E, hipStream_t s);
+// work doubles for dots() with up to k vectors and for norm_inf_2()
+size_t reduce_work_doubles(int n, int k);
+
+// Event timing of all-pairs launches (diagnostics).
+struct ProfileMark {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+ProfileMark profile_begin(hipStream_t s);
+void profile_end(const ProfileMark& m, hipStream_t s, double pairs);
 
 // zeta on the grid from u (trapezoid integration of zeta_x)
 void zeta_enqueue(const Geo& g, const double* u, double* zeta, hipStream_t s);

@@ -1,0 +1,125 @@
+"""Preconditioner apply and Newton-Krylov solve on the GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import flat_state as oflat
+from oracle import linear as OL
+from oracle.equations import residual_rows, row_scale, zeta_grid
+from oracle.equations import residual as oresidual
+from oracle.solve import newton
+from paper_1403_5044_amd import api, inputs
+
+from gpu_common import dev, gprob, host, log, oprob
+
+pytestmark = pytest.mark.gpu
+
+TINY = dict(N=9, M=5, x1=-3.0, xN=3.0, yM=2.0, F=0.7, eps=0.3)
+SMALL = dict(N=15, M=7, x1=-6.0, xN=6.0, yM=5.0, F=0.7, eps=0.05)
+
+
+@pytest.mark.parametrize("cfg", [TINY, SMALL, inputs.CONFIG1,
+                                 dict(N=41, M=13, x1=-8.0, xN=8.0, yM=6.0, F=0.9, eps=0.1,
+                                      weights="simpson")])
+def test_preconditioner_apply_matches_dense_solve(cfg):
+    p = gprob(cfg)
+    op = oprob(p)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(p.n_unknowns)
+    for q in sorted({0, 1, 2, p.M - 1}):
+        pre_o = OL.BlockPreconditioner(op, q)
+        Pm = pre_o.matrix()
+        P = api.Preconditioner(p, q)
+        x = host(P.apply(dev(b)))
+        P.close()
+        res = np.abs(Pm @ x - b).max() / (np.abs(Pm).max() * np.abs(x).max())
+        xo = pre_o.solve(b)
+        rel = np.abs(x - xo).max() / np.abs(xo).max()
+        log(f"N={p.N} M={p.M} q={q}: backward err {res:.2e}, vs oracle {rel:.2e}")
+        assert res <= 1e-13
+        assert rel <= 1e-8
+
+
+def test_preconditioner_apply_in_place():
+    p = gprob(inputs.CONFIG1)
+    b = np.random.default_rng(1).standard_normal(p.n_unknowns)
+    P = api.Preconditioner(p, 1)
+    x1 = host(P.apply(dev(b)))
+    bd = dev(b)
+    P.apply(bd, out=bd)
+    assert np.array_equal(host(bd), x1)
+    P.close()
+
+
+def _oracle_root(p, tol=1e-12):
+    op = oprob(p)
+    u, info = newton(op, oflat(op), tol=tol)
+    assert info.converged
+    return u
+
+
+@pytest.mark.parametrize("q", [0, 1, 10])
+def test_config1_fp64_solve_matches_oracle_root(q):
+    p = gprob(inputs.CONFIG1)
+    uo = _oracle_root(p)
+    u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, q_blocks=q, tol=1e-11)
+    log(f"config1 q={q}: {info}")
+    assert info.status == 0
+    ug = host(u)
+    zg = host(z)
+    zo = zeta_grid(oprob(p), uo).ravel()
+    assert np.abs(zg - zo).max() <= 1e-8
+    assert np.abs(ug - uo).max() <= 1e-7
+    assert np.abs(oresidual(oprob(p), ug)).max() <= 2e-11
+    assert zg.max() <= p.F ** 2 / 2
+
+
+def test_config1_mixed_precision_solve_within_stated_bound():
+    p = gprob(inputs.CONFIG1)
+    uo = _oracle_root(p)
+    u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
+                           tol=1e-10)
+    log(f"config1 mixed: {info}")
+    assert info.status == 0
+    zo = zeta_grid(oprob(p), uo).ravel()
+    err = np.abs(host(z) - zo).max()
+    log(f"config1 mixed zeta err {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_solve_continuation_from_caller_state():
+    p = gprob(inputs.CONFIG1)
+    u, _, info = api.solve(p.F, 0.05, p.N, p.M, p.x1, p.xN, p.yM)
+    assert info.status == 0
+    u2, z2, info2 = api.solve(p.F, 0.1, p.N, p.M, p.x1, p.xN, p.yM, u0=u)
+    assert info2.status == 0
+    uo = _oracle_root(p.with_(eps=0.1))
+    zo = zeta_grid(oprob(p.with_(eps=0.1)), uo).ravel()
+    assert np.abs(host(z2) - zo).max() <= 1e-8
+
+
+def test_config2_solve_is_a_root_of_the_oracle_system():
+    """Config 2 (181 x 61, eps 0.1): the GPU root, checked by the oracle on
+    every E1/E4/E6 entry and on sampled E2 entries; FP32-mixed root agrees."""
+    p = gprob(inputs.CONFIG2)
+    u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, tol=1e-10)
+    log(f"config2 fp64: {info}")
+    assert info.status == 0
+    ug = host(u)
+    op = oprob(p)
+    NM = p.N * p.M
+    rng = np.random.default_rng(0)
+    e2 = NM + rng.integers(0, p.M, 40) * p.N + rng.integers(1, p.N, 40)
+    rows = np.unique(np.concatenate([np.arange(NM), e2]))
+    Eo, _ = residual_rows(op, ug, rows)
+    log(f"config2 oracle |E(u_gpu)| max {np.abs(Eo).max():.2e}")
+    assert np.abs(Eo).max() <= 1e-9
+    zg = host(z)
+    assert zg.max() <= p.F ** 2 / 2
+    um, zm, infom = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
+                              tol=1e-10)
+    log(f"config2 mixed: {infom}")
+    assert infom.status == 0
+    err = np.abs(host(zm) - zg).max()
+    log(f"config2 mixed vs fp64 zeta {err:.2e}")
+    assert err <= 1e-6

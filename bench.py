@@ -41,7 +41,28 @@ def parse():
     ap.add_argument("--q", type=int, default=4, help="preconditioner block half-bandwidth")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving workload: Poisson arrivals of mixed solves (prints its own line)")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per all-pairs launch from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pairs_f64_181x61_hbm_counters.json")
+    src = os.path.join(ROOT, "paper_1403_5044_amd", "csrc", "residual.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, evals_per_solve):
@@ -73,6 +94,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        return calibrate_copy()
+    if args.serving:
+        return serving(args)
     import torch
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
@@ -113,7 +138,8 @@ def main():
     flops_per_launch = FLOP_PER_PAIR * pairs / max(launches, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic(),
                 "kernel": "k_pairs_f64 (all-pairs boundary-integral sum)",
                 "launches": launches, "avg_launch_ms": avg_ms,
                 "flop_per_launch": flops_per_launch}
@@ -180,6 +206,83 @@ def extra_measurements(api, inputs, cfg, one_solve):
     res["solve_mixed_iters"] = [infom.newton_iters, infom.gmres_iters, infom.residual_evals]
     P.close()
     return res
+
+
+def calibrate_copy():
+    """Three copies of 1 GiB between device buffers (torch's copy kernel): the
+    reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "dispatches": 3}))
+
+
+def serving(args):
+    """Serving workload: requests with Poisson arrivals, meshes uniform over
+    {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
+    F ~ U[0.5, 1.0], eps ~ U[0.05, 0.4] (seed 0).  First a closed-loop run
+    (all requests at once) measures the mixed-precision capacity; the arrival
+    rate is set to 80% of it.  Then the same arrival sequence is served in
+    mixed precision (FP32-Kahan inner JVPs, FP64 fallback) and in plain FP64,
+    each by a warmed server (preconditioners cached per mesh and F bucket)."""
+    import numpy as np
+    from paper_1403_5044_amd import api, inputs
+    from paper_1403_5044_amd import _lib
+    _lib.load()
+    dom = inputs.SERVING_DOMAIN
+
+    def run(srv, reqs, rate=None):
+        t0 = time.perf_counter()
+        tickets = []
+        for (ta, N, M, F, eps) in reqs:
+            if rate is not None:
+                delay = ta - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(F, eps, N, M, dom["x1"], dom["xN"], dom["yM"]))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        res = [srv.poll(t) for t in tickets]
+        lat = np.array([r.t_done_s - r.t_submit_s for r in res])
+        ok = sum(1 for r in res if r.status == 0)
+        return {"requests": len(res), "converged": ok,
+                "fallbacks": sum(r.used_fallback for r in res),
+                "wall_s": wall, "solves_per_s": len(res) / wall,
+                "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)),
+                "mean_newton": float(np.mean([r.newton_iters for r in res])),
+                "mean_gmres": float(np.mean([r.gmres_iters for r in res])),
+                "mean_evals": float(np.mean([r.residual_evals for r in res]))}
+
+    base = inputs.serving_requests(args.requests, 1.0, 0)
+    out = {}
+    servers = {}
+    for prec in ("fp32", "fp64"):
+        servers[prec] = api.Server(hbm_budget_bytes=64e9, max_slots=32, precision=prec,
+                                   fallback_fp64=True, q_blocks=args.q)
+        out[f"closed_loop_{prec}"] = run(servers[prec], base)   # warms the caches
+    capacity = out["closed_loop_fp32"]["solves_per_s"]
+    rate = 0.8 * capacity
+    reqs = inputs.serving_requests(args.requests, rate, 0)
+    for prec in ("fp32", "fp64"):
+        out[f"poisson_{prec}"] = run(servers[prec], reqs, rate=rate)
+        servers[prec].close()
+    line = {"metric": "JFNK solves/s & pair-interactions/s (frac FP64 peak); p50/p99 solve latency",
+            "value": out["poisson_fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.requests, "warmup": args.requests, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": (f"serving: {args.requests} requests, Poisson arrivals at "
+                                    f"{rate:.2f}/s (80% of closed-loop mixed capacity), meshes "
+                                    f"61x21/121x41/181x61/241x81, F~U[0.5,1], eps~U[0.05,0.4], "
+                                    f"seed 0, q={args.q}")},
+            "p50_latency_s": out["poisson_fp32"]["p50_latency_s"],
+            "p99_latency_s": out["poisson_fp32"]["p99_latency_s"],
+            "arrival_rate_per_s": rate, "runs": out}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

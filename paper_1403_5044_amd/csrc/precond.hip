@@ -41,6 +41,7 @@ struct sw_precond {
     double* tmp2 = nullptr;  // [q][N][N] products of one factorisation step
     int* info = nullptr;     // [M] zero pivots seen
     void* terms = nullptr;   // device GemvTerm lists of the band substitution steps
+    hipGraphExec_t subst = nullptr;  // the 2M substitution launches, captured once
     std::vector<int> fwd_off, fwd_cnt, bwd_off, bwd_cnt;
     size_t bytes = 0;
     int device = -1;
@@ -192,66 +193,25 @@ __global__ __launch_bounds__(256) void k_assemble(Geo g, int q, const double* __
     }
 }
 
-// In-place inverses of N x N blocks (row-major), one workgroup per block:
-// Gauss-Jordan with partial (row) pivoting.  The row interchanges are undone at
-// the end by permuting columns: interchanging columns p and ipiv[p] for
-// p = N-1 .. 0 moves column src[j] of the eliminated matrix to position j,
-// with src built by the same interchanges on an index array.
+// Inverses of N x N blocks (row-major), one workgroup per block: Gauss-Jordan
+// with partial pivoting done implicitly.  Rows are never swapped: step p
+// eliminates column p with the unused physical row rp of largest |B[rp][p]|,
+// storing the inverse's columns in place of the eliminated ones.  With
+// rowpiv[p] = rp and step_of[rp] = p the inverse is
+//     A^{-1}[step_of[r]][rowpiv[c]] = B[r][c],
+// written by one scatter at the end.  The pivot search of step p+1 runs inside
+// the update of step p (look-ahead), so each step needs two barriers.
 constexpr int kGJ = 1024;
 
-// Largest |v| (smallest index on ties) over the block; result in (*pv, *pi) for all threads.
-__device__ void block_argmax(double bv, int bi, double* redv, int* redi, int* out_i) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int d = 32; d >= 1; d >>= 1) {
-        const double ov = __shfl_xor(bv, d, 64);
-        const int oi = __shfl_xor(bi, d, 64);
-        if (ov > bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
-        }
-    }
-    if (lane == 0) {
-        redv[wid] = bv;
-        redi[wid] = bi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double v = redv[0];
-        int i = redi[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-            if (redv[w] > v || (redv[w] == v && redi[w] < i)) {
-                v = redv[w];
-                i = redi[w];
-            }
-        *out_i = i;
-    }
-    __syncthreads();
-}
-
-__device__ void unscramble_order(int N, const int* ipiv, int* src) {
-    if (threadIdx.x == 0) {
-        for (int j = 0; j < N; ++j) src[j] = j;
-        for (int p = N - 1; p >= 0; --p) {
-            const int q = ipiv[p];
-            const int t = src[p];
-            src[p] = src[q];
-            src[q] = t;
-        }
-    }
-    __syncthreads();
-}
-
-// Matrix in registers: thread (ty = t / 64, tx = t % 64) holds A[ty + 16 i][tx + 64 c].
+// Matrix in registers: thread (ty = t / 64, tx = t % 64) holds B[ty + 16 i][tx + 64 c].
 template <int RB, int CB>
 __global__ __launch_bounds__(kGJ) void k_gj_reg(int N, double* __restrict__ base, size_t stride,
                                                 int* __restrict__ info) {
     double* A = base + (size_t)blockIdx.x * stride;
-    __shared__ double rowp[64 * CB], rowq[64 * CB], colp[16 * RB];
-    __shared__ int ipiv[64 * CB], dst[64 * CB];
-    __shared__ double redv[kGJ / 64];
-    __shared__ int redi[kGJ / 64];
-    __shared__ int piv_s;
-    __shared__ double app_s;
+    __shared__ double rowp[64 * CB], colp[16 * RB];
+    __shared__ double candv[2][16];
+    __shared__ int candr[2][16];
+    __shared__ int rowpiv[64 * CB], step_of[16 * RB];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double a[RB][CB];
 #pragma unroll
@@ -261,175 +221,201 @@ __global__ __launch_bounds__(kGJ) void k_gj_reg(int N, double* __restrict__ base
             const int r = ty + 16 * i, j = tx + 64 * c;
             a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
         }
+    unsigned used = 0;  // bit i: row ty + 16 i has been a pivot
+    if (tx == 0) {
+        double bv = -1.0;
+        int br = N;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = ty + 16 * i;
+            const double v = fabs(a[i][0]);
+            if (r < N && v > bv) {
+                bv = v;
+                br = r;
+            }
+        }
+        candv[0][ty] = bv;
+        candr[0][ty] = br;
+    }
+    __syncthreads();
     int zero_pivots = 0;
     for (int p = 0; p < N; ++p) {
-        const int pc = p >> 6, pt = p & 63;
+        const int buf = p & 1;
         double bv = -1.0;
-        int bi = N;
-        if (tx == pt) {
+        int rp = N;
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int r = ty + 16 * i;
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c == pc && r >= p && r < N) {
-                        const double v = fabs(a[i][c]);
-                        if (v > bv) {
-                            bv = v;
-                            bi = r;
-                        }
-                    }
+        for (int w = 0; w < 16; ++w) {
+            const double v = candv[buf][w];
+            const int r = candr[buf][w];
+            if (v > bv || (v == bv && r < rp)) {
+                bv = v;
+                rp = r;
             }
         }
-        block_argmax(bv, bi, redv, redi, &piv_s);
-        int pv = piv_s;
-        if (pv >= N) pv = p;
-        if (threadIdx.x == 0) ipiv[p] = pv;
-        // rows p and pv through LDS
-        if (pv != p) {
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int r = ty + 16 * i;
-#pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    if (r == pv) rowq[tx + 64 * c] = a[i][c];
-                    if (r == p) rowp[tx + 64 * c] = a[i][c];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int r = ty + 16 * i;
-#pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    if (r == p) a[i][c] = rowq[tx + 64 * c];
-                    if (r == pv) a[i][c] = rowp[tx + 64 * c];
-                }
-            }
-            __syncthreads();
+        if (ty == (rp & 15)) used |= 1u << (rp >> 4);
+        if (threadIdx.x == 0) {
+            rowpiv[p] = rp;
+            step_of[rp] = p;
         }
-        // pivot row and column to LDS
+        const int pc = p >> 6, pt = p & 63;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
             const int r = ty + 16 * i;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                if (r == p) rowp[tx + 64 * c] = a[i][c];
+                if (r == rp) rowp[tx + 64 * c] = a[i][c];
                 if (c == pc && tx == pt) colp[r] = a[i][c];
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) app_s = rowp[p];
-        __syncthreads();
-        const double app = app_s;
-        if (app == 0.0) ++zero_pivots;
-        const double dinv = 1.0 / app;
+        const double piv = rowp[p];
+        if (piv == 0.0) ++zero_pivots;
+        const double d = 1.0 / piv;
+        const int p1 = p + 1, p1c = p1 >> 6, p1t = p1 & 63;
+        double nb = -1.0;
+        int nr = N;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int j = tx + 64 * c;
-            const double rp = (j == p) ? dinv : rowp[j] * dinv;
+            const double rpj = (j == p) ? d : rowp[j] * d;
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int r = ty + 16 * i;
-                if (r == p)
-                    a[i][c] = rp;
+                if (r == rp)
+                    a[i][c] = rpj;
                 else
-                    a[i][c] = fma(-colp[r], rp, (j == p) ? 0.0 : a[i][c]);
+                    a[i][c] = fma(-colp[r], rpj, (j == p) ? 0.0 : a[i][c]);
+                if (c == p1c && tx == p1t && r < N && !((used >> i) & 1u)) {
+                    const double v = fabs(a[i][c]);
+                    if (v > nb) {
+                        nb = v;
+                        nr = r;
+                    }
+                }
             }
+        }
+        if (tx == p1t) {
+            candv[buf ^ 1][ty] = nb;
+            candr[buf ^ 1][ty] = nr;
         }
         __syncthreads();
     }
-    unscramble_order(N, ipiv, dst);  // dst holds src[] here
-    // column src[j] of the eliminated matrix goes to column j: invert the map
-    __shared__ int inv[64 * CB];
-    for (int j = threadIdx.x; j < N; j += kGJ) inv[dst[j]] = j;
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int r = ty + 16 * i, j = tx + 64 * c;
-            if (r < N && j < N) A[(size_t)r * N + inv[j]] = a[i][c];
+            if (r < N && j < N) A[(size_t)step_of[r] * N + rowpiv[j]] = a[i][c];
         }
     if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_pivots;
 }
 
-// Matrix in global memory (any N <= kMaxN): thread (ty, tx) sweeps rows ty, ty+16, ...
-// and columns tx, tx+64, ...
+// Matrix in global memory (any N <= kMaxN): thread (ty, tx) updates rows ty, ty+16, ...
+// and columns tx, tx+64, ...  The inverse is scattered into `out` (not `base`).
 __global__ __launch_bounds__(kGJ) void k_gj_global(int N, double* __restrict__ base,
-                                                   size_t stride, int* __restrict__ info) {
-    double* A = base + (size_t)blockIdx.x * stride;
-    __shared__ double rowp[kMaxN];
-    __shared__ double colp[kMaxN];
-    __shared__ int ipiv[kMaxN], srcmap[kMaxN], inv[kMaxN];
-    __shared__ double redv[kGJ / 64];
-    __shared__ int redi[kGJ / 64];
-    __shared__ int piv_s;
+                                                   size_t stride, double* __restrict__ outbase,
+                                                   size_t out_stride, int* __restrict__ info) {
+    double* B = base + (size_t)blockIdx.x * stride;
+    double* O = outbase + (size_t)blockIdx.x * out_stride;
+    __shared__ double rowp[kMaxN], colp[kMaxN];
+    __shared__ double candv[2][16];
+    __shared__ int candr[2][16];
+    __shared__ int rowpiv[kMaxN], step_of[kMaxN];
+    __shared__ unsigned char used[kMaxN];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    int zero_pivots = 0;
-    for (int p = 0; p < N; ++p) {
+    for (int r = threadIdx.x; r < N; r += kGJ) used[r] = 0;
+    if (tx == 0) {
         double bv = -1.0;
-        int bi = N;
-        for (int r = p + threadIdx.x; r < N; r += kGJ) {
-            const double v = fabs(A[(size_t)r * N + p]);
+        int br = N;
+        for (int r = ty; r < N; r += 16) {
+            const double v = fabs(B[(size_t)r * N]);
             if (v > bv) {
                 bv = v;
-                bi = r;
+                br = r;
             }
         }
-        block_argmax(bv, bi, redv, redi, &piv_s);
-        int pv = piv_s;
-        if (pv >= N) pv = p;
-        if (threadIdx.x == 0) ipiv[p] = pv;
-        if (pv != p)
-            for (int j = threadIdx.x; j < N; j += kGJ) {
-                const double t = A[(size_t)p * N + j];
-                A[(size_t)p * N + j] = A[(size_t)pv * N + j];
-                A[(size_t)pv * N + j] = t;
+        candv[0][ty] = bv;
+        candr[0][ty] = br;
+    }
+    __syncthreads();
+    int zero_pivots = 0;
+    for (int p = 0; p < N; ++p) {
+        const int buf = p & 1;
+        double bv = -1.0;
+        int rp = N;
+        for (int w = 0; w < 16; ++w) {
+            const double v = candv[buf][w];
+            const int r = candr[buf][w];
+            if (v > bv || (v == bv && r < rp)) {
+                bv = v;
+                rp = r;
             }
+        }
+        if (threadIdx.x == 0) {
+            rowpiv[p] = rp;
+            step_of[rp] = p;
+            used[rp] = 1;
+        }
+        for (int j = threadIdx.x; j < N; j += kGJ) rowp[j] = B[(size_t)rp * N + j];
+        for (int r = threadIdx.x; r < N; r += kGJ) colp[r] = B[(size_t)r * N + p];
         __syncthreads();
-        const double app = A[(size_t)p * N + p];
-        if (app == 0.0) ++zero_pivots;
-        const double dinv = 1.0 / app;
-        for (int j = threadIdx.x; j < N; j += kGJ)
-            rowp[j] = (j == p) ? dinv : A[(size_t)p * N + j] * dinv;
-        for (int r = threadIdx.x; r < N; r += kGJ) colp[r] = A[(size_t)r * N + p];
-        __syncthreads();
+        const double piv = rowp[p];
+        if (piv == 0.0) ++zero_pivots;
+        const double d = 1.0 / piv;
+        const int p1 = p + 1;
+        double nb = -1.0;
+        int nr = N;
         for (int r = ty; r < N; r += 16) {
+            double* row = B + (size_t)r * N;
             const double cr = colp[r];
-            double* row = A + (size_t)r * N;
-            if (r == p) {
-                for (int j = tx; j < N; j += 64) row[j] = rowp[j];
-            } else {
-                for (int j = tx; j < N; j += 64)
-                    row[j] = fma(-cr, rowp[j], (j == p) ? 0.0 : row[j]);
+            const bool isp = (r == rp);
+            const bool cand = !used[r];
+            for (int j = tx; j < N; j += 64) {
+                const double rpj = (j == p) ? d : rowp[j] * d;
+                const double v = isp ? rpj : fma(-cr, rpj, (j == p) ? 0.0 : row[j]);
+                row[j] = v;
+                if (j == p1 && cand && fabs(v) > nb) {
+                    nb = fabs(v);
+                    nr = r;
+                }
             }
+        }
+        if (tx == (p1 & 63)) {
+            candv[buf ^ 1][ty] = nb;
+            candr[buf ^ 1][ty] = nr;
         }
         __syncthreads();
     }
-    unscramble_order(N, ipiv, srcmap);
-    for (int j = threadIdx.x; j < N; j += kGJ) inv[srcmap[j]] = j;
-    __syncthreads();
-    // permute columns of each row through LDS
-    for (int r = 0; r < N; ++r) {
-        double* row = A + (size_t)r * N;
-        for (int j = threadIdx.x; j < N; j += kGJ) rowp[inv[j]] = row[j];
-        __syncthreads();
-        for (int j = threadIdx.x; j < N; j += kGJ) row[j] = rowp[j];
-        __syncthreads();
+    for (int r = ty; r < N; r += 16) {
+        const double* row = B + (size_t)r * N;
+        double* orow = O + (size_t)step_of[r] * N;
+        for (int j = tx; j < N; j += 64) orow[rowpiv[j]] = row[j];
     }
     if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_pivots;
 }
 
-void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, hipStream_t s) {
-    if (N <= 64)
+__global__ void k_copy_blocks(size_t n, const double* __restrict__ a, double* __restrict__ b) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x)
+        b[t] = a[t];
+}
+
+// Inverts nblocks blocks in place; tmp: nblocks x N x N doubles, used for N > 192.
+void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, double* tmp,
+                hipStream_t s) {
+    if (N <= 64) {
         k_gj_reg<4, 1><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
-    else if (N <= 128)
+    } else if (N <= 128) {
         k_gj_reg<8, 2><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
-    else if (N <= 192)
+    } else if (N <= 192) {
         k_gj_reg<12, 3><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
-    else
-        k_gj_global<<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+    } else {
+        const size_t NN = (size_t)N * N;
+        k_gj_global<<<nblocks, kGJ, 0, s>>>(N, base, stride, tmp, NN, info);
+        for (int b = 0; b < nblocks; ++b)
+            k_copy_blocks<<<(unsigned)std::min<size_t>((NN + 255) / 256, 4096), 256, 0, s>>>(
+                NN, tmp + (size_t)b * NN, base + (size_t)b * stride);
+    }
 }
 
 // C = Cin + alpha A B for N x N row-major blocks (C may equal Cin, not A or B);
@@ -634,6 +620,11 @@ void copy(size_t n, const double* a, double* b, hipStream_t s) {
 }  // namespace
 
 namespace {
+// scratch blocks: q products per factorisation step, or M inverses at once (q = 0, N > 192)
+size_t tmp2_blocks(const Geo& g, int q) {
+    return (size_t)std::max({q, 1, (q == 0 && g.N > 192) ? g.M : 1});
+}
+
 int k3_chunks(const Geo& g) {
     const int ntile = (g.ncol + 255) / 256;
     return std::max(1, std::min(g.M, (4096 + ntile - 1) / ntile));
@@ -646,7 +637,7 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const size_t N = g.N, NN = N * N, NM = g.NM;
     const int G = k3_chunks(g);
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8, NN * 8,
-                       (size_t)std::max(q, 1) * NN * 8, (size_t)g.M * 4, (size_t)G * g.ncol * 8,
+                       tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4, (size_t)G * g.ncol * 8,
                        NN * 8});
 }
 
@@ -655,6 +646,10 @@ size_t precond_bytes(const sw_precond* P) { return P ? P->bytes : 0; }
 bool precond_matches(const sw_precond* P, const Geo& g) {
     return P && P->g.N == g.N && P->g.M == g.M && P->g.x1 == g.x1 && P->g.xN == g.xN &&
            P->g.yM == g.yM;
+}
+
+namespace {
+void capture_substitution(sw_precond* P);
 }
 
 sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
@@ -685,7 +680,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->k3 = c.take<double>(g.ncol);
     P->work = c.take<double>(4 * NM);
     P->tmp = c.take<double>(NN);
-    P->tmp2 = c.take<double>((size_t)std::max(q, 1) * NN);
+    P->tmp2 = c.take<double>(tmp2_blocks(g, q) * NN);
     P->info = c.take<int>(g.M);
     double* part = c.take<double>((size_t)G * g.ncol);
     double* X = c.take<double>(NN);
@@ -698,11 +693,11 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         k_assemble<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>(
             g, q, P->k3, P->Wc, P->S);
         if (q == 0) {
-            gj_inverse(g.N, P->S, NN, g.M, P->info, s);
+            gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, s);
         } else {
             double* scratchL = P->tmp2;  // q blocks for L_{i,l} and G_{l,j}
             for (int l = 0; l < g.M; ++l) {
-                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, s);
+                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, P->tmp2, s);
                 const int hi = std::min(g.M - 1, l + q);
                 const int cnt = hi - l;
                 if (cnt == 0) continue;
@@ -762,6 +757,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
             SW_HIP(hipMalloc(&P->terms, tv.size() * sizeof(GemvTerm)));
             SW_HIP(hipMemcpy(P->terms, tv.data(), tv.size() * sizeof(GemvTerm),
                              hipMemcpyHostToDevice));
+            capture_substitution(P);
         }
         SW_HIP(hipGetLastError());
         std::vector<int> info(g.M);
@@ -773,11 +769,57 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(P->base);
         if (P->terms) (void)hipFree(P->terms);
+        if (P->subst) (void)hipGraphExecDestroy(P->subst);
         delete P;
         throw;
     }
     return P;
 }
+
+namespace {
+// Block forward and backward substitution with the band factors (q >= 1); all
+// pointers live in the preconditioner, so the sequence can be captured once.
+void enqueue_substitution(const sw_precond* P, hipStream_t s) {
+    const Geo& g = P->g;
+    const size_t NM = g.NM;
+    const int N = g.N;
+    double* t2 = P->work + NM;
+    double* s2 = P->work + 2 * NM;
+    double* tmp = P->work + 3 * NM;
+    const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);
+    const unsigned blocks = (unsigned)((N * 64 + 255) / 256);
+    // forward: y_l = t_l - sum_d L_{l,l-d} y_{l-d}   (y in tmp)
+    for (int l = 0; l < g.M; ++l)
+        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->fwd_off[l], P->fwd_cnt[l],
+                                           t2 + (size_t)l * N, tmp + (size_t)l * N);
+    // backward: x_l = Dinv_l y_l - sum_d G_{l,l+d} x_{l+d}   (x in s2)
+    for (int l = g.M - 1; l >= 0; --l)
+        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->bwd_off[l], P->bwd_cnt[l], nullptr,
+                                           s2 + (size_t)l * N);
+}
+
+// Capture the substitution launches into an executable graph (kernel nodes only).
+void capture_substitution(sw_precond* P) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        enqueue_substitution(P, cs);
+        ok = hipStreamEndCapture(cs, &graph) == hipSuccess && graph != nullptr;
+    }
+    if (ok) ok = hipGraphInstantiate(&P->subst, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        P->subst = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+}
+}  // namespace
 
 void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t s) {
     const Geo& g = P->g;
@@ -785,23 +827,15 @@ void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t 
     double* s1 = P->work;
     double* t2 = P->work + NM;
     double* s2 = P->work + 2 * NM;
-    double* tmp = P->work + 3 * NM;
     k_apply_first<<<g.M, 64, 0, s>>>(g, b, s1, t2);
     const int N = g.N;
     if (P->q == 0) {
         const int rows = N * g.M;
         k_blockdiag_gemv<<<(rows * 64 + 255) / 256, 256, 0, s>>>(N, g.M, P->S, t2, s2);
+    } else if (P->subst) {
+        SW_HIP(hipGraphLaunch(P->subst, s));
     } else {
-        const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);
-        const unsigned blocks = (unsigned)((N * 64 + 255) / 256);
-        // forward: y_l = t_l - sum_d L_{l,l-d} y_{l-d}   (y in tmp)
-        for (int l = 0; l < g.M; ++l)
-            k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->fwd_off[l], P->fwd_cnt[l],
-                                               t2 + (size_t)l * N, tmp + (size_t)l * N);
-        // backward: x_l = Dinv_l y_l - sum_d G_{l,l+d} x_{l+d}   (x in s2)
-        for (int l = g.M - 1; l >= 0; --l)
-            k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->bwd_off[l], P->bwd_cnt[l], nullptr,
-                                               s2 + (size_t)l * N);
+        enqueue_substitution(P, s);
     }
     k_apply_last<<<g.M, 64, 0, s>>>(g, s1, s2, x);
     SW_HIP(hipGetLastError());
@@ -815,6 +849,7 @@ void precond_destroy(sw_precond* P) {
     (void)hipDeviceSynchronize();
     (void)hipFree(P->base);
     if (P->terms) (void)hipFree(P->terms);
+    if (P->subst) (void)hipGraphExecDestroy(P->subst);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(cur);
     delete P;
 }

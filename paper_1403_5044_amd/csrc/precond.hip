@@ -310,6 +310,184 @@ __global__ __launch_bounds__(kGJ) void k_gj_reg(int N, double* __restrict__ base
     if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_pivots;
 }
 
+// Blocked form of the same elimination for N <= 64 * CB (matrix in registers).
+// Panels of kPB pivot columns: one wavefront eliminates the panel columns in
+// LDS (pivot search by shuffles, no block barriers), recording for every row r
+// and panel step t the multiplier m_t[r] (column p_t of row r just before step
+// t).  The other columns then receive all kPB steps at once:
+//   Z_t = d_t (B_{rp_t} - sum_{s<t} m_s[rp_t] Z_s)     (pivot rows, kPB x N)
+//   B_r <- B_r - sum_t m_t[r] Z_t                       (other rows)
+//   B_{rp_t} <- Z_t - sum_{s>t} m_s[rp_t] Z_s            (pivot rows)
+// which equals applying the kPB elementary steps one after another.
+constexpr int kPB = 8;
+
+template <int RB, int CB>
+__global__ __launch_bounds__(kGJ) void k_gj_blocked(int N, double* __restrict__ base,
+                                                    size_t stride, int* __restrict__ info) {
+    constexpr int R = 16 * RB, C = 64 * CB;
+    double* A = base + (size_t)blockIdx.x * stride;
+    __shared__ double Pn[R][kPB];   // panel columns
+    __shared__ double Mt[R][kPB];   // multipliers m_t[r]
+    __shared__ double Zr[kPB][C];   // pivot rows before the panel (non-panel columns)
+    __shared__ double Zz[kPB][C];   // Z_t
+    __shared__ double W[kPB][kPB];
+    __shared__ int rowpiv[C], step_of[R];
+    __shared__ int used[R];
+    __shared__ int zero_s;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double a[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int r = ty + 16 * i, j = tx + 64 * c;
+            a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
+        }
+    for (int r = threadIdx.x; r < R; r += kGJ) {
+        step_of[r] = -1;
+        used[r] = 0;
+    }
+    for (int e = threadIdx.x; e < kPB * C; e += kGJ) Zz[e / C][e % C] = 0.0;
+    if (threadIdx.x == 0) zero_s = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < N; k0 += kPB) {
+        const int kb = min(kPB, N - k0);
+        const int c0 = k0 >> 6, t0 = k0 & 63;
+        // ---- panel to LDS
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (c == c0 && tx >= t0 && tx < t0 + kb)
+#pragma unroll
+                for (int i = 0; i < RB; ++i) Pn[ty + 16 * i][tx - t0] = a[i][c];
+        __syncthreads();
+        // ---- panel elimination by wavefront 0
+        if (ty == 0) {
+            for (int t = 0; t < kb; ++t) {
+                const int p = k0 + t;
+                double bv = -1.0;
+                int br = N;
+                for (int r = tx; r < N; r += 64)
+                    if (!used[r]) {
+                        const double v = fabs(Pn[r][t]);
+                        if (v > bv) {
+                            bv = v;
+                            br = r;
+                        }
+                    }
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const double ov = __shfl_xor(bv, d, 64);
+                    const int orr = __shfl_xor(br, d, 64);
+                    if (ov > bv || (ov == bv && orr < br)) {
+                        bv = ov;
+                        br = orr;
+                    }
+                }
+                const int rp = br;
+                double prow[kPB];
+#pragma unroll
+                for (int u = 0; u < kPB; ++u) prow[u] = Pn[rp][u];
+                const double piv = Pn[rp][t];
+                const double dd = 1.0 / piv;
+                __builtin_amdgcn_wave_barrier();
+                if (tx == 0) {
+                    rowpiv[p] = rp;
+                    step_of[rp] = p;
+                    used[rp] = 1;
+                    if (piv == 0.0) zero_s++;
+                }
+                for (int r = tx; r < N; r += 64) {
+                    const double m = Pn[r][t];
+                    Mt[r][t] = m;
+                    if (r == rp) {
+#pragma unroll
+                        for (int u = 0; u < kPB; ++u) Pn[r][u] = (u == t) ? dd : prow[u] * dd;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < kPB; ++u)
+                            Pn[r][u] = (u == t) ? -m * dd : fma(-m, prow[u] * dd, Pn[r][u]);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        }
+        __syncthreads();
+        // W with Z = W B0p; the pivot value of step t is Mt[rp_t][t]
+        if (threadIdx.x == 0) {
+            for (int t = 0; t < kb; ++t) {
+                const int rt = rowpiv[k0 + t];
+                const double dt = 1.0 / Mt[rt][t];
+                for (int u = 0; u < kPB; ++u) W[t][u] = 0.0;
+                W[t][t] = dt;
+                for (int s2 = 0; s2 < t; ++s2) {
+                    const double ms = Mt[rt][s2];
+                    for (int u = 0; u <= s2; ++u) W[t][u] -= dt * ms * W[s2][u];
+                }
+            }
+        }
+        // ---- panel back to registers; pivot rows' other columns to LDS
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (c == c0 && tx >= t0 && tx < t0 + kb)
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    const int r = ty + 16 * i;
+                    if (r < N) a[i][c] = Pn[r][tx - t0];
+                }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = ty + 16 * i;
+            const int st = (r < N) ? step_of[r] : -1;
+            if (st >= k0 && st < k0 + kb)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) Zr[st - k0][tx + 64 * c] = a[i][c];
+        }
+        __syncthreads();
+        // ---- Z = W Zr
+        if (ty < kb) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int j = tx + 64 * c;
+                double z = 0.0;
+                for (int u = 0; u <= ty; ++u) z = fma(W[ty][u], Zr[u][j], z);
+                Zz[ty][j] = z;
+            }
+        }
+        __syncthreads();
+        // ---- rank-kb update of the non-panel columns
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = ty + 16 * i;
+            if (r >= N) continue;
+            const int st = step_of[r];
+            const bool isp = (st >= k0 && st < k0 + kb);
+            const int tp = isp ? st - k0 : -1;
+            double coef[kPB];
+#pragma unroll
+            for (int u = 0; u < kPB; ++u) coef[u] = (u < kb && u > tp) ? Mt[r][u] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int j = tx + 64 * c;
+                const bool inpanel = (c == c0 && tx >= t0 && tx < t0 + kb);
+                if (inpanel) continue;
+                double v = isp ? Zz[tp][j] : a[i][c];
+#pragma unroll
+                for (int u = 0; u < kPB; ++u) v = fma(-coef[u], Zz[u][j], v);
+                a[i][c] = v;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int r = ty + 16 * i, j = tx + 64 * c;
+            if (r < N && j < N) A[(size_t)step_of[r] * N + rowpiv[j]] = a[i][c];
+        }
+    if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_s;
+}
+
 // Matrix in global memory (any N <= kMaxN): thread (ty, tx) updates rows ty, ty+16, ...
 // and columns tx, tx+64, ...  The inverse is scattered into `out` (not `base`).
 __global__ __launch_bounds__(kGJ) void k_gj_global(int N, double* __restrict__ base,
@@ -404,11 +582,11 @@ __global__ void k_copy_blocks(size_t n, const double* __restrict__ a, double* __
 void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, double* tmp,
                 hipStream_t s) {
     if (N <= 64) {
-        k_gj_reg<4, 1><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_blocked<4, 1><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
     } else if (N <= 128) {
-        k_gj_reg<8, 2><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_blocked<8, 2><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
     } else if (N <= 192) {
-        k_gj_reg<12, 3><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_blocked<12, 3><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
     } else {
         const size_t NN = (size_t)N * N;
         k_gj_global<<<nblocks, kGJ, 0, s>>>(N, base, stride, tmp, NN, info);
@@ -565,14 +743,41 @@ struct GemvTerm {
     double pad;
 };
 
+constexpr int kMaxTerms = 16;
+
 __global__ __launch_bounds__(256) void k_band_step(int N, const GemvTerm* __restrict__ terms,
                                                    int nterms, const double* __restrict__ add,
                                                    double* __restrict__ out) {
     const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wid >= N) return;
+    // term pointers in registers (uniform), then one pass over the columns with the
+    // loads of every term issued together
+    const double* rows[kMaxTerms];
+    const double* vecs[kMaxTerms];
+    double sg[kMaxTerms];
+    const int nt = min(nterms, kMaxTerms);
+#pragma unroll
+    for (int q = 0; q < kMaxTerms; ++q) {
+        if (q < nt) {
+            const GemvTerm tm = terms[q];
+            rows[q] = tm.blk + (size_t)wid * N;
+            vecs[q] = tm.vec;
+            sg[q] = tm.sign;
+        } else {
+            rows[q] = nullptr;
+            vecs[q] = nullptr;
+            sg[q] = 0.0;
+        }
+    }
     double s = 0.0;
-    for (int q = 0; q < nterms; ++q) {
+    for (int n = lane; n < N; n += 64) {
+#pragma unroll
+        for (int q = 0; q < kMaxTerms; ++q)
+            if (q < nt) s = fma(sg[q] * rows[q][n], vecs[q][n], s);
+    }
+    // terms beyond kMaxTerms (q > 15) in a second sweep
+    for (int q = kMaxTerms; q < nterms; ++q) {
         const GemvTerm tm = terms[q];
         const double* row = tm.blk + (size_t)wid * N;
         double p = 0.0;

@@ -278,9 +278,10 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
                                                double* __restrict__ partial, int tile, int chunk,
                                                int G, double* lds) {
     const int tid = threadIdx.x;
-    const int j0 = (int)((long long)chunk * g.M / G);
-    const int j1 = (int)((long long)(chunk + 1) * g.M / G);
     const int N = g.N;
+    // this chunk's sources: a contiguous range of the row-major source index
+    const int s0 = (int)((long long)chunk * g.NM / G);
+    const int s1 = (int)((long long)(chunk + 1) * g.NM / G);
     double xs[CP], zs[CP], ps[CP], zxs[CP], A[CP], B[CP], C[CP];
     double acc1[CP], acc2[CP], acc3[CP];
     int idx[CP], lrow[CP];
@@ -301,12 +302,13 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
         C[c] = 1.0 + zy * zy;
         acc1[c] = acc2[c] = acc3[c] = 0.0;
     }
-    for (int j = j0; j < j1; ++j) {
+    for (int j = s0 / N; j * N < s1; ++j) {
+        const int i0 = max(0, s0 - j * N), i1 = min(N, s1 - j * N);
         __syncthreads();
         {
             const double2* srow = reinterpret_cast<const double2*>(src + (size_t)j * N * 8);
             double2* dst = reinterpret_cast<double2*>(lds);
-            for (int t = tid; t < N * 4; t += kPairThreads) dst[t] = srow[t];
+            for (int t = i0 * 4 + tid; t < i1 * 4; t += kPairThreads) dst[t] = srow[t];
         }
         __syncthreads();
         double dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
@@ -322,11 +324,11 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
             Cdyp2[c] = C[c] * dyp2[c];
         }
 #pragma unroll 2
-        for (int i = 0; i < N; ++i) {
-            const double4 s0 = reinterpret_cast<const double4*>(lds + i * 8)[0];
-            const double4 s1 = reinterpret_cast<const double4*>(lds + i * 8)[1];
-            const double sx = s0.x, sz = s0.y, szx = s0.z, szy = s0.w;
-            const double swp = s1.x, sw = s1.y, swzx = s1.z;
+        for (int i = i0; i < i1; ++i) {
+            const double4 r0 = reinterpret_cast<const double4*>(lds + i * 8)[0];
+            const double4 r1 = reinterpret_cast<const double4*>(lds + i * 8)[1];
+            const double sx = r0.x, sz = r0.y, szx = r0.z, szy = r0.w;
+            const double swp = r1.x, sw = r1.y, swzx = r1.z;
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
                 const double dx = sx - xs[c];
@@ -383,9 +385,9 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
                                                double* __restrict__ partial, int tile, int chunk,
                                                int G, float* lds) {
     const int tid = threadIdx.x;
-    const int j0 = (int)((long long)chunk * g.M / G);
-    const int j1 = (int)((long long)(chunk + 1) * g.M / G);
     const int N = g.N;
+    const int lo = (int)((long long)chunk * g.NM / G);
+    const int hi = (int)((long long)(chunk + 1) * g.NM / G);
     const float fdx = (float)g.dx;
     float t0[CP], zs[CP], ps[CP], zxs[CP], A[CP], B[CP], C[CP];
     float S[CP], comp[CP];
@@ -407,12 +409,13 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
         C[c] = (float)(1.0 + r1.y * r1.y);
         S[c] = comp[c] = 0.0f;
     }
-    for (int j = j0; j < j1; ++j) {
+    for (int j = lo / N; j * N < hi; ++j) {
+        const int i0 = max(0, lo - j * N), i1 = min(N, hi - j * N);
         __syncthreads();
         {
             const float4* srow = reinterpret_cast<const float4*>(src + (size_t)j * N * 8);
             float4* dst = reinterpret_cast<float4*>(lds);
-            for (int t = tid; t < N * 2; t += kPairThreads) dst[t] = srow[t];
+            for (int t = i0 * 2 + tid; t < i1 * 2; t += kPairThreads) dst[t] = srow[t];
         }
         __syncthreads();
         float dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
@@ -430,7 +433,7 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
             r1[c] = r2[c] = r3[c] = 0.0f;
         }
 #pragma unroll 2
-        for (int i = 0; i < N; ++i) {
+        for (int i = i0; i < i1; ++i) {
             const float4 s0 = reinterpret_cast<const float4*>(lds + i * 8)[0];
             const float4 s1 = reinterpret_cast<const float4*>(lds + i * 8)[1];
 #pragma unroll
@@ -594,12 +597,11 @@ const double* spline_operator(int M, int bc, hipStream_t s) {
 int choose_chunks(const Geo& g) {
     const int cp = (g.precision == SW_PREC_FP32) ? kCP32 : kCP64;
     const int ntiles = (g.ncol + kPairThreads * cp - 1) / (kPairThreads * cp);
-#ifndef SW_PAIR_BLOCKS
-#define SW_PAIR_BLOCKS 4096
-#endif
-    const int target = SW_PAIR_BLOCKS;
-    int G = (target + ntiles - 1) / ntiles;
-    return std::max(1, std::min(G, g.M));
+    // About 2048 equal blocks: two full rounds at four 256-thread blocks per CU.
+    // A chunk keeps at least 64 sources so that staging it in LDS pays off.
+    const int target = 2048;
+    const int G = (target + ntiles / 2) / ntiles;
+    return std::max(1, std::min(G, g.NM / 64));
 }
 
 size_t residual_scratch_bytes(const Geo& g, int G) {

@@ -37,7 +37,7 @@ struct sw_precond {
     double* Wc = nullptr;    // [N][N]
     double* k3 = nullptr;    // [ncol] sum w K3
     double* work = nullptr;  // [4][NM]
-    double* tmp = nullptr;   // [N][N]
+    double* tmp = nullptr;   // workspace of the diagonal-block inversion
     double* tmp2 = nullptr;  // [q][N][N] products of one factorisation step
     int* info = nullptr;     // [M] zero pivots seen
     void* terms = nullptr;   // device GemvTerm lists of the band substitution steps
@@ -193,409 +193,408 @@ __global__ __launch_bounds__(256) void k_assemble(Geo g, int q, const double* __
     }
 }
 
-// Inverses of N x N blocks (row-major), one workgroup per block: Gauss-Jordan
-// with partial pivoting done implicitly.  Rows are never swapped: step p
-// eliminates column p with the unused physical row rp of largest |B[rp][p]|,
-// storing the inverse's columns in place of the eliminated ones.  With
+// ---- inverses of the diagonal blocks ----------------------------------------------------
+// Gauss-Jordan with partial pivoting done implicitly: rows are never swapped.
+// Step p eliminates column p with the unused row rp of largest |B[rp][p]| and
+// stores the inverse's column in place of the eliminated one.  With
 // rowpiv[p] = rp and step_of[rp] = p the inverse is
 //     A^{-1}[step_of[r]][rowpiv[c]] = B[r][c],
-// written by one scatter at the end.  The pivot search of step p+1 runs inside
-// the update of step p (look-ahead), so each step needs two barriers.
-constexpr int kGJ = 1024;
+// written by one scatter at the end.
+//
+// Blocked form.  The columns are taken in panels of w.  The panel alone (all
+// rows, w columns) is eliminated first; its pivot rows R_0..R_{w-1} and new
+// columns Pn follow (rows R_t of Pn hold W = (B[R][panel])^{-1}, any other row r
+// holds -B[r][panel] W).  Every column outside the panel then receives the w
+// steps at once through the old pivot rows Z_t = B[R_t]:
+//     B[r][j] <- base_r[j] + sum_t Pn[r][t] Z_t[j],   base_r = 0 if r is in R, else B[r],
+// which is the Schur complement B - B[:,panel] W B[R,:] on the other rows and
+// W B[R,:] on the pivot rows, i.e. the same as taking the w steps one by one.
 
-// Matrix in registers: thread (ty = t / 64, tx = t % 64) holds B[ty + 16 i][tx + 64 c].
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Maximum over each row of 16 lanes, left in every lane of that row
+// (quad swaps, then half-row and row mirrors).  NaN operands are dropped by fmax.
+__device__ __forceinline__ double row16_max_f64(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_f64<0x141>(v));  // row_half_mirror
+    v = fmax(v, dpp_f64<0x140>(v));  // row_mirror
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+    v = row16_max_f64(v);
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+                fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// ---- N <= 192: the whole block in registers, one workgroup ----
+// Thread (tr = t / 32, tc = t % 32) holds B[tr + 16 i][tc + 32 c].  Wavefront 0
+// eliminates each panel of kPW columns with rows lane + 64 i in registers (pivot
+// search by DPP and readlane, no block barrier); all threads then apply the
+// rank-kPW update from LDS.
+constexpr int kGT = 512;
+constexpr int kPW = 8;
+
 template <int RB, int CB>
-__global__ __launch_bounds__(kGJ) void k_gj_reg(int N, double* __restrict__ base, size_t stride,
-                                                int* __restrict__ info) {
+__global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ base, size_t stride,
+                                                 int* __restrict__ info) {
+    constexpr int R = 16 * RB, C = 32 * CB, RW = R / 64;
+    static_assert(R == C && RW * 64 == R, "square tile, whole rows per lane of one wave");
     double* A = base + (size_t)blockIdx.x * stride;
-    __shared__ double rowp[64 * CB], colp[16 * RB];
-    __shared__ double candv[2][16];
-    __shared__ int candr[2][16];
-    __shared__ int rowpiv[64 * CB], step_of[16 * RB];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    __shared__ double Pn[R][kPW];
+    __shared__ double Zr[kPW][C];
+    __shared__ int rowpiv[C], step_of[R];
+    const int t = threadIdx.x;
+    const int tc = t & 31, tr = t >> 5, lane = t & 63;
+    const bool w0 = t < 64;
     double a[RB][CB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int r = ty + 16 * i, j = tx + 64 * c;
+            const int r = tr + 16 * i, j = tc + 32 * c;
             a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
         }
-    unsigned used = 0;  // bit i: row ty + 16 i has been a pivot
-    if (tx == 0) {
-        double bv = -1.0;
-        int br = N;
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r = ty + 16 * i;
-            const double v = fabs(a[i][0]);
-            if (r < N && v > bv) {
-                bv = v;
-                br = r;
-            }
-        }
-        candv[0][ty] = bv;
-        candr[0][ty] = br;
+    for (int r = t; r < R; r += kGT) {
+        step_of[r] = -1;
+        rowpiv[r] = -1;
     }
-    __syncthreads();
-    int zero_pivots = 0;
-    for (int p = 0; p < N; ++p) {
-        const int buf = p & 1;
-        double bv = -1.0;
-        int rp = N;
+    unsigned usedm = 0;  // wavefront 0: bit i marks row lane + 64 i as pivoted or padding
 #pragma unroll
-        for (int w = 0; w < 16; ++w) {
-            const double v = candv[buf][w];
-            const int r = candr[buf][w];
-            if (v > bv || (v == bv && r < rp)) {
-                bv = v;
-                rp = r;
+    for (int i = 0; i < RW; ++i)
+        if (lane + 64 * i >= N) usedm |= 1u << i;
+    int zeros = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < N; k0 += kPW) {
+        const int kb = min(kPW, N - k0);
+        const int c0 = k0 >> 5, t0 = k0 & 31;  // kPW divides 32: a panel never straddles c
+        const bool pcol = tc >= t0 && tc < t0 + kPW;
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (c == c0 && pcol)
+#pragma unroll
+                for (int i = 0; i < RB; ++i) Pn[tr + 16 * i][tc - t0] = a[i][c];
+        __syncthreads();
+        if (w0) {
+            double pv[RW][kPW];
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) pv[i][u] = Pn[lane + 64 * i][u];
+#pragma unroll
+            for (int s = 0; s < kPW; ++s) {
+                if (s >= kb) break;
+                double best = -1.0;
+                int bi = -1;
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    const double v = fabs(pv[i][s]);
+                    if (!((usedm >> i) & 1u) && (bi < 0 || v > best)) {
+                        best = v;
+                        bi = i;
+                    }
+                }
+                const double mx = wave_max_f64(best);
+                unsigned long long mask = __ballot(bi >= 0 && best == mx);
+                if (mask == 0) mask = __ballot(bi >= 0);  // the column holds NaN
+                const int pl = mask ? __builtin_ctzll(mask) : 0;
+                const int pi = max(0, __builtin_amdgcn_readlane(bi, pl));
+                const int rp = pl + 64 * pi;
+                double prow[kPW];
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) prow[u] = 0.0;
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+                    if (i == pi)
+#pragma unroll
+                        for (int u = 0; u < kPW; ++u) prow[u] = readlane_f64(pv[i][u], pl);
+                const double piv = prow[s];
+                if (!(fabs(piv) > 0.0)) ++zeros;
+                const double d = 1.0 / piv;
+                double pd[kPW];
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) pd[u] = (u == s) ? d : prow[u] * d;
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    const double m = pv[i][s];
+#pragma unroll
+                    for (int u = 0; u < kPW; ++u)
+                        pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
+                }
+                if (lane == pl) {
+#pragma unroll
+                    for (int i = 0; i < RW; ++i)
+                        if (i == pi) {
+#pragma unroll
+                            for (int u = 0; u < kPW; ++u) pv[i][u] = pd[u];
+                            usedm |= 1u << i;
+                        }
+                }
+                if (lane == 0) {
+                    rowpiv[k0 + s] = rp;
+                    step_of[rp] = k0 + s;
+                }
             }
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) Pn[lane + 64 * i][u] = pv[i][u];
         }
-        if (ty == (rp & 15)) used |= 1u << (rp >> 4);
-        if (threadIdx.x == 0) {
-            rowpiv[p] = rp;
-            step_of[rp] = p;
-        }
-        const int pc = p >> 6, pt = p & 63;
+        __syncthreads();
+        // old pivot rows to Zr; their base becomes zero
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-            const int r = ty + 16 * i;
+            const int r = tr + 16 * i;
+            const int st = step_of[r];
+            if (st >= k0 && st < k0 + kb) {
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                if (r == rp) rowp[tx + 64 * c] = a[i][c];
-                if (c == pc && tx == pt) colp[r] = a[i][c];
+                for (int c = 0; c < CB; ++c) {
+                    Zr[st - k0][tc + 32 * c] = a[i][c];
+                    a[i][c] = 0.0;
+                }
             }
         }
         __syncthreads();
-        const double piv = rowp[p];
-        if (piv == 0.0) ++zero_pivots;
-        const double d = 1.0 / piv;
-        const int p1 = p + 1, p1c = p1 >> 6, p1t = p1 & 63;
-        double nb = -1.0;
-        int nr = N;
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int j = tx + 64 * c;
-            const double rpj = (j == p) ? d : rowp[j] * d;
+        for (int u = 0; u < kPW; ++u) {
+            if (u >= kb) break;
+            double z[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) z[c] = Zr[u][tc + 32 * c];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
-                const int r = ty + 16 * i;
-                if (r == rp)
-                    a[i][c] = rpj;
-                else
-                    a[i][c] = fma(-colp[r], rpj, (j == p) ? 0.0 : a[i][c]);
-                if (c == p1c && tx == p1t && r < N && !((used >> i) & 1u)) {
-                    const double v = fabs(a[i][c]);
-                    if (v > nb) {
-                        nb = v;
-                        nr = r;
-                    }
-                }
+                const double p = Pn[tr + 16 * i][u];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) a[i][c] = fma(p, z[c], a[i][c]);
             }
         }
-        if (tx == p1t) {
-            candv[buf ^ 1][ty] = nb;
-            candr[buf ^ 1][ty] = nr;
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int r = ty + 16 * i, j = tx + 64 * c;
-            if (r < N && j < N) A[(size_t)step_of[r] * N + rowpiv[j]] = a[i][c];
-        }
-    if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_pivots;
-}
-
-// Blocked form of the same elimination for N <= 64 * CB (matrix in registers).
-// Panels of kPB pivot columns: one wavefront eliminates the panel columns in
-// LDS (pivot search by shuffles, no block barriers), recording for every row r
-// and panel step t the multiplier m_t[r] (column p_t of row r just before step
-// t).  The other columns then receive all kPB steps at once:
-//   Z_t = d_t (B_{rp_t} - sum_{s<t} m_s[rp_t] Z_s)     (pivot rows, kPB x N)
-//   B_r <- B_r - sum_t m_t[r] Z_t                       (other rows)
-//   B_{rp_t} <- Z_t - sum_{s>t} m_s[rp_t] Z_s            (pivot rows)
-// which equals applying the kPB elementary steps one after another.
-constexpr int kPB = 8;
-
-template <int RB, int CB>
-__global__ __launch_bounds__(kGJ) void k_gj_blocked(int N, double* __restrict__ base,
-                                                    size_t stride, int* __restrict__ info) {
-    constexpr int R = 16 * RB, C = 64 * CB;
-    double* A = base + (size_t)blockIdx.x * stride;
-    __shared__ double Pn[R][kPB];   // panel columns
-    __shared__ double Mt[R][kPB];   // multipliers m_t[r]
-    __shared__ double Zr[kPB][C];   // pivot rows before the panel (non-panel columns)
-    __shared__ double Zz[kPB][C];   // Z_t
-    __shared__ double W[kPB][kPB];
-    __shared__ int rowpiv[C], step_of[R];
-    __shared__ int used[R];
-    __shared__ int zero_s;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    double a[RB][CB];
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int r = ty + 16 * i, j = tx + 64 * c;
-            a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
-        }
-    for (int r = threadIdx.x; r < R; r += kGJ) {
-        step_of[r] = -1;
-        used[r] = 0;
-    }
-    for (int e = threadIdx.x; e < kPB * C; e += kGJ) Zz[e / C][e % C] = 0.0;
-    if (threadIdx.x == 0) zero_s = 0;
-    __syncthreads();
-    for (int k0 = 0; k0 < N; k0 += kPB) {
-        const int kb = min(kPB, N - k0);
-        const int c0 = k0 >> 6, t0 = k0 & 63;
-        // ---- panel to LDS
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            if (c == c0 && tx >= t0 && tx < t0 + kb)
+            if (c == c0 && pcol)
 #pragma unroll
-                for (int i = 0; i < RB; ++i) Pn[ty + 16 * i][tx - t0] = a[i][c];
-        __syncthreads();
-        // ---- panel elimination by wavefront 0
-        if (ty == 0) {
-            for (int t = 0; t < kb; ++t) {
-                const int p = k0 + t;
-                double bv = -1.0;
-                int br = N;
-                for (int r = tx; r < N; r += 64)
-                    if (!used[r]) {
-                        const double v = fabs(Pn[r][t]);
-                        if (v > bv) {
-                            bv = v;
-                            br = r;
-                        }
-                    }
-                for (int d = 32; d >= 1; d >>= 1) {
-                    const double ov = __shfl_xor(bv, d, 64);
-                    const int orr = __shfl_xor(br, d, 64);
-                    if (ov > bv || (ov == bv && orr < br)) {
-                        bv = ov;
-                        br = orr;
-                    }
-                }
-                const int rp = br;
-                double prow[kPB];
-#pragma unroll
-                for (int u = 0; u < kPB; ++u) prow[u] = Pn[rp][u];
-                const double piv = Pn[rp][t];
-                const double dd = 1.0 / piv;
-                __builtin_amdgcn_wave_barrier();
-                if (tx == 0) {
-                    rowpiv[p] = rp;
-                    step_of[rp] = p;
-                    used[rp] = 1;
-                    if (piv == 0.0) zero_s++;
-                }
-                for (int r = tx; r < N; r += 64) {
-                    const double m = Pn[r][t];
-                    Mt[r][t] = m;
-                    if (r == rp) {
-#pragma unroll
-                        for (int u = 0; u < kPB; ++u) Pn[r][u] = (u == t) ? dd : prow[u] * dd;
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < kPB; ++u)
-                            Pn[r][u] = (u == t) ? -m * dd : fma(-m, prow[u] * dd, Pn[r][u]);
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            }
-        }
-        __syncthreads();
-        // W with Z = W B0p; the pivot value of step t is Mt[rp_t][t]
-        if (threadIdx.x == 0) {
-            for (int t = 0; t < kb; ++t) {
-                const int rt = rowpiv[k0 + t];
-                const double dt = 1.0 / Mt[rt][t];
-                for (int u = 0; u < kPB; ++u) W[t][u] = 0.0;
-                W[t][t] = dt;
-                for (int s2 = 0; s2 < t; ++s2) {
-                    const double ms = Mt[rt][s2];
-                    for (int u = 0; u <= s2; ++u) W[t][u] -= dt * ms * W[s2][u];
-                }
-            }
-        }
-        // ---- panel back to registers; pivot rows' other columns to LDS
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            if (c == c0 && tx >= t0 && tx < t0 + kb)
-#pragma unroll
-                for (int i = 0; i < RB; ++i) {
-                    const int r = ty + 16 * i;
-                    if (r < N) a[i][c] = Pn[r][tx - t0];
-                }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r = ty + 16 * i;
-            const int st = (r < N) ? step_of[r] : -1;
-            if (st >= k0 && st < k0 + kb)
-#pragma unroll
-                for (int c = 0; c < CB; ++c) Zr[st - k0][tx + 64 * c] = a[i][c];
-        }
-        __syncthreads();
-        // ---- Z = W Zr
-        if (ty < kb) {
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int j = tx + 64 * c;
-                double z = 0.0;
-                for (int u = 0; u <= ty; ++u) z = fma(W[ty][u], Zr[u][j], z);
-                Zz[ty][j] = z;
-            }
-        }
-        __syncthreads();
-        // ---- rank-kb update of the non-panel columns
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r = ty + 16 * i;
-            if (r >= N) continue;
-            const int st = step_of[r];
-            const bool isp = (st >= k0 && st < k0 + kb);
-            const int tp = isp ? st - k0 : -1;
-            double coef[kPB];
-#pragma unroll
-            for (int u = 0; u < kPB; ++u) coef[u] = (u < kb && u > tp) ? Mt[r][u] : 0.0;
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int j = tx + 64 * c;
-                const bool inpanel = (c == c0 && tx >= t0 && tx < t0 + kb);
-                if (inpanel) continue;
-                double v = isp ? Zz[tp][j] : a[i][c];
-#pragma unroll
-                for (int u = 0; u < kPB; ++u) v = fma(-coef[u], Zz[u][j], v);
-                a[i][c] = v;
-            }
-        }
+                for (int i = 0; i < RB; ++i) a[i][c] = Pn[tr + 16 * i][tc - t0];
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int r = ty + 16 * i, j = tx + 64 * c;
-            if (r < N && j < N) A[(size_t)step_of[r] * N + rowpiv[j]] = a[i][c];
+            const int r = tr + 16 * i, j = tc + 32 * c;
+            if (r < N && j < N) {
+                const int sr = step_of[r], pj = rowpiv[j];
+                if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
+            }
         }
-    if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_s;
+    if (t == 0 && info) info[blockIdx.x] = zeros;
 }
 
-// Matrix in global memory (any N <= kMaxN): thread (ty, tx) updates rows ty, ty+16, ...
-// and columns tx, tx+64, ...  The inverse is scattered into `out` (not `base`).
-__global__ __launch_bounds__(kGJ) void k_gj_global(int N, double* __restrict__ base,
-                                                   size_t stride, double* __restrict__ outbase,
-                                                   size_t out_stride, int* __restrict__ info) {
-    double* B = base + (size_t)blockIdx.x * stride;
-    double* O = outbase + (size_t)blockIdx.x * out_stride;
-    __shared__ double rowp[kMaxN], colp[kMaxN];
-    __shared__ double candv[2][16];
-    __shared__ int candr[2][16];
-    __shared__ int rowpiv[kMaxN], step_of[kMaxN];
-    __shared__ unsigned char used[kMaxN];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = threadIdx.x; r < N; r += kGJ) used[r] = 0;
-    if (tx == 0) {
-        double bv = -1.0;
-        int br = N;
-        for (int r = ty; r < N; r += 16) {
-            const double v = fabs(B[(size_t)r * N]);
-            if (v > bv) {
-                bv = v;
-                br = r;
-            }
+// ---- N > 192: the block in global memory, one panel and one update launch per panel ----
+// Panel kernel: one workgroup per block, thread r holds row r of the panel (N <= 1024).
+// Pivot search: DPP maximum per wavefront, then over the 16 wavefront candidates.
+// It writes the new panel columns pn[N][kPWG], the old pivot rows z[kPWG][N],
+// step_of[N] and rowpiv[N] (per block, in the workspace gjw).
+constexpr int kGP = 1024;
+constexpr int kPWG = 16;
+
+struct GjWork {
+    double* pn;   // [nblocks][N][kPWG]
+    double* z;    // [nblocks][kPWG][N]
+    int* piv;     // [nblocks][2][N]: step_of, rowpiv
+};
+
+__global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restrict__ base,
+                                                   size_t stride, GjWork w, int k0,
+                                                   int* __restrict__ info) {
+    const double* B = base + (size_t)blockIdx.x * stride;
+    double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
+    double* z = w.z + (size_t)blockIdx.x * kPWG * N;
+    int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
+    int* rowpiv = step_of + N;
+    __shared__ double candv[16], prow[kPWG];
+    __shared__ int candr[16], rp_s[kPWG];
+    const int r = threadIdx.x, lane = r & 63, wv = r >> 6;
+    const int kb = min(kPWG, N - k0);
+    const bool valid = r < N;
+    int st = (valid && k0 > 0) ? step_of[r] : -1;
+    double pv[kPWG];
+#pragma unroll
+    for (int u = 0; u < kPWG; ++u)
+        pv[u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
+    int zeros = 0;
+#pragma unroll
+    for (int s = 0; s < kPWG; ++s) {
+        if (s >= kb) break;
+        const bool cand = valid && st < 0;
+        const double v = cand ? fabs(pv[s]) : -1.0;
+        const double wm = wave_max_f64(v);
+        unsigned long long mask = __ballot(cand && v == wm);
+        if (mask == 0) mask = __ballot(cand);
+        if (lane == 0) {
+            candv[wv] = mask ? wm : -2.0;
+            candr[wv] = mask ? (wv * 64 + __builtin_ctzll(mask)) : -1;
         }
-        candv[0][ty] = bv;
-        candr[0][ty] = br;
-    }
-    __syncthreads();
-    int zero_pivots = 0;
-    for (int p = 0; p < N; ++p) {
-        const int buf = p & 1;
-        double bv = -1.0;
-        int rp = N;
-        for (int w = 0; w < 16; ++w) {
-            const double v = candv[buf][w];
-            const int r = candr[buf][w];
-            if (v > bv || (v == bv && r < rp)) {
-                bv = v;
-                rp = r;
-            }
-        }
-        if (threadIdx.x == 0) {
-            rowpiv[p] = rp;
-            step_of[rp] = p;
-            used[rp] = 1;
-        }
-        for (int j = threadIdx.x; j < N; j += kGJ) rowp[j] = B[(size_t)rp * N + j];
-        for (int r = threadIdx.x; r < N; r += kGJ) colp[r] = B[(size_t)r * N + p];
         __syncthreads();
-        const double piv = rowp[p];
-        if (piv == 0.0) ++zero_pivots;
+        const double cv = (lane < 16) ? candv[lane] : -2.0;
+        const int cr = (lane < 16) ? candr[lane] : -1;
+        const double gm = readlane_f64(row16_max_f64(cv), 0);
+        unsigned long long m2 = __ballot(cr >= 0 && cv == gm);
+        if (m2 == 0) m2 = __ballot(cr >= 0);
+        const int rp = m2 ? __builtin_amdgcn_readlane(cr, __builtin_ctzll(m2)) : 0;
+        if (r == rp)
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) prow[u] = pv[u];
+        __syncthreads();
+        double pd[kPWG];
+#pragma unroll
+        for (int u = 0; u < kPWG; ++u) pd[u] = prow[u];
+        const double piv = pd[s];
         const double d = 1.0 / piv;
-        const int p1 = p + 1;
-        double nb = -1.0;
-        int nr = N;
-        for (int r = ty; r < N; r += 16) {
-            double* row = B + (size_t)r * N;
-            const double cr = colp[r];
-            const bool isp = (r == rp);
-            const bool cand = !used[r];
-            for (int j = tx; j < N; j += 64) {
-                const double rpj = (j == p) ? d : rowp[j] * d;
-                const double v = isp ? rpj : fma(-cr, rpj, (j == p) ? 0.0 : row[j]);
-                row[j] = v;
-                if (j == p1 && cand && fabs(v) > nb) {
-                    nb = fabs(v);
-                    nr = r;
-                }
-            }
+#pragma unroll
+        for (int u = 0; u < kPWG; ++u) pd[u] = (u == s) ? d : pd[u] * d;
+        if (r == rp) {
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) pv[u] = pd[u];
+            st = k0 + s;
+        } else {
+            const double m = pv[s];
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) pv[u] = (u == s) ? -m * d : fma(-m, pd[u], pv[u]);
         }
-        if (tx == (p1 & 63)) {
-            candv[buf ^ 1][ty] = nb;
-            candr[buf ^ 1][ty] = nr;
+        if (r == 0) {
+            rp_s[s] = rp;
+            rowpiv[k0 + s] = rp;
+            if (!(fabs(piv) > 0.0)) ++zeros;
         }
-        __syncthreads();
     }
-    for (int r = ty; r < N; r += 16) {
-        const double* row = B + (size_t)r * N;
-        double* orow = O + (size_t)step_of[r] * N;
-        for (int j = tx; j < N; j += 64) orow[rowpiv[j]] = row[j];
+    if (valid) {
+#pragma unroll
+        for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[u];
+        step_of[r] = st;
     }
-    if (threadIdx.x == 0 && info) info[blockIdx.x] = zero_pivots;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kb * N; e += kGP) {
+        const int tt = e / N, j = e - tt * N;
+        z[(size_t)tt * N + j] = B[(size_t)rp_s[tt] * N + j];
+    }
+    if (r == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
 
-__global__ void k_copy_blocks(size_t n, const double* __restrict__ a, double* __restrict__ b) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (size_t)gridDim.x * blockDim.x)
-        b[t] = a[t];
+// Rank-kb update of every column outside the panel; the panel columns take pn.
+// Tile of 16 rows x 64 columns per 256-thread workgroup; grid (cols, rows, blocks).
+__global__ __launch_bounds__(256) void k_gjp_update(int N, double* __restrict__ base,
+                                                    size_t stride, GjWork w, int k0) {
+    double* B = base + (size_t)blockIdx.z * stride;
+    const double* pn = w.pn + (size_t)blockIdx.z * N * kPWG;
+    const double* z = w.z + (size_t)blockIdx.z * kPWG * N;
+    const int* step_of = w.piv + (size_t)blockIdx.z * 2 * N;
+    const int kb = min(kPWG, N - k0);
+    __shared__ double ps[16][kPWG], zs[kPWG][64];
+    __shared__ int isp[16];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int row0 = blockIdx.y * 16, col0 = blockIdx.x * 64;
+    {
+        const int rr = threadIdx.x >> 4, u = threadIdx.x & 15;
+        const int gr = row0 + rr;
+        ps[rr][u] = (gr < N && u < kb) ? pn[(size_t)gr * kPWG + u] : 0.0;
+        if (u == 0) {
+            const int st = (gr < N) ? step_of[gr] : -1;
+            isp[rr] = (st >= k0 && st < k0 + kb);
+        }
+    }
+    for (int e = threadIdx.x; e < kPWG * 64; e += 256) {
+        const int u = e >> 6, c = e & 63, gc = col0 + c;
+        zs[u][c] = (u < kb && gc < N) ? z[(size_t)u * N + gc] : 0.0;
+    }
+    __syncthreads();
+    const int j = col0 + tx;
+    if (j >= N) return;
+    const bool inpanel = j >= k0 && j < k0 + kb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = ty + 4 * i, gr = row0 + rr;
+        if (gr >= N) break;
+        double* p = B + (size_t)gr * N + j;
+        if (inpanel) {
+            *p = ps[rr][j - k0];
+        } else {
+            double v = isp[rr] ? 0.0 : *p;
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) v = fma(ps[rr][u], zs[u][tx], v);
+            *p = v;
+        }
+    }
 }
 
-// Inverts nblocks blocks in place; tmp: nblocks x N x N doubles, used for N > 192.
+// out[step_of[r]][rowpiv[c]] = B[r][c]; grid (elements, blocks)
+__global__ void k_gjp_scatter(int N, const double* __restrict__ base, size_t stride,
+                              double* __restrict__ outbase, size_t out_stride, GjWork w) {
+    const double* B = base + (size_t)blockIdx.y * stride;
+    double* O = outbase + (size_t)blockIdx.y * out_stride;
+    const int* step_of = w.piv + (size_t)blockIdx.y * 2 * N;
+    const int* rowpiv = step_of + N;
+    const size_t NN = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < NN;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
+        const int sr = step_of[r], pc = rowpiv[c];
+        if (sr >= 0 && sr < N && pc >= 0 && pc < N) O[(size_t)sr * N + pc] = B[e];
+    }
+}
+
+__global__ void k_copy_blocks(int N, const double* __restrict__ a, size_t a_stride,
+                              double* __restrict__ b, size_t b_stride) {
+    const size_t NN = (size_t)N * N;
+    const double* src = a + (size_t)blockIdx.y * a_stride;
+    double* dst = b + (size_t)blockIdx.y * b_stride;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < NN;
+         e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+size_t gj_work_doubles(int N, int nblocks) {
+    return N > 192 ? (size_t)nblocks * (2 * kPWG + 1) * N : 0;
+}
+
+// Inverts nblocks blocks in place.  For N > 192: tmp holds nblocks x N x N
+// doubles (the scattered inverses) and work gj_work_doubles(N, nblocks).
 void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, double* tmp,
-                hipStream_t s) {
+                double* work, hipStream_t s) {
     if (N <= 64) {
-        k_gj_blocked<4, 1><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_tile<4, 2><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 128) {
-        k_gj_blocked<8, 2><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_tile<8, 4><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 192) {
-        k_gj_blocked<12, 3><<<nblocks, kGJ, 0, s>>>(N, base, stride, info);
+        k_gj_tile<12, 6><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else {
         const size_t NN = (size_t)N * N;
-        k_gj_global<<<nblocks, kGJ, 0, s>>>(N, base, stride, tmp, NN, info);
-        for (int b = 0; b < nblocks; ++b)
-            k_copy_blocks<<<(unsigned)std::min<size_t>((NN + 255) / 256, 4096), 256, 0, s>>>(
-                NN, tmp + (size_t)b * NN, base + (size_t)b * stride);
+        GjWork w;
+        w.pn = work;
+        w.z = work + (size_t)nblocks * N * kPWG;
+        w.piv = reinterpret_cast<int*>(work + (size_t)nblocks * 2 * kPWG * N);
+        const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
+        for (int k0 = 0; k0 < N; k0 += kPWG) {
+            k_gjp_panel<<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+            k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);
+        }
+        const unsigned ge = (unsigned)std::min<size_t>((NN + 255) / 256, 2048);
+        k_gjp_scatter<<<dim3(ge, nblocks), 256, 0, s>>>(N, base, stride, tmp, NN, w);
+        k_copy_blocks<<<dim3(ge, nblocks), 256, 0, s>>>(N, tmp, NN, base, stride);
     }
 }
-
 // C = Cin + alpha A B for N x N row-major blocks (C may equal Cin, not A or B);
 // blockIdx.z selects one of a list of such products.
 struct GemmJob {
@@ -830,6 +829,12 @@ size_t tmp2_blocks(const Geo& g, int q) {
     return (size_t)std::max({q, 1, (q == 0 && g.N > 192) ? g.M : 1});
 }
 
+// workspace of the diagonal-block inversion (N > 192), at least one N x N block
+size_t gj_work_size(const Geo& g, int q) {
+    const size_t NN = (size_t)g.N * g.N;
+    return std::max(NN, gj_work_doubles(g.N, q == 0 ? g.M : 1));
+}
+
 int k3_chunks(const Geo& g) {
     const int ntile = (g.ncol + 255) / 256;
     return std::max(1, std::min(g.M, (4096 + ntile - 1) / ntile));
@@ -841,8 +846,8 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
     const int G = k3_chunks(g);
-    return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8, NN * 8,
-                       tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4, (size_t)G * g.ncol * 8,
+    return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
+                       gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4, (size_t)G * g.ncol * 8,
                        NN * 8});
 }
 
@@ -884,7 +889,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->Wc = c.take<double>(NN);
     P->k3 = c.take<double>(g.ncol);
     P->work = c.take<double>(4 * NM);
-    P->tmp = c.take<double>(NN);
+    P->tmp = c.take<double>(gj_work_size(g, q));
     P->tmp2 = c.take<double>(tmp2_blocks(g, q) * NN);
     P->info = c.take<int>(g.M);
     double* part = c.take<double>((size_t)G * g.ncol);
@@ -898,11 +903,12 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         k_assemble<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>(
             g, q, P->k3, P->Wc, P->S);
         if (q == 0) {
-            gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, s);
+            gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
         } else {
             double* scratchL = P->tmp2;  // q blocks for L_{i,l} and G_{l,j}
             for (int l = 0; l < g.M; ++l) {
-                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, P->tmp2, s);
+                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, P->tmp2, P->tmp,
+                           s);
                 const int hi = std::min(g.M - 1, l + q);
                 const int cnt = hi - l;
                 if (cnt == 0) continue;

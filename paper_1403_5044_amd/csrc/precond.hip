@@ -28,6 +28,20 @@
 #include <cmath>
 #include <vector>
 
+namespace sw {
+// One step of the super-row substitution: out rows of block row i are
+//   out_i[r] = sum over t in [first[i], first[i+1]) of blk[t][r][:] . vec[t][:]
+// (blk: N x N row-major operator blocks, vec: input blocks of length N).
+constexpr int kMaxSuperRows = 16;
+constexpr int kMaxSuperTerms = 184;
+struct SuperStep {
+    int nrow;
+    int first[kMaxSuperRows + 1];
+    const double* blk[kMaxSuperTerms];
+    const double* vec[kMaxSuperTerms];
+};
+}  // namespace sw
+
 struct sw_precond {
     sw::Geo g;
     int q;
@@ -38,11 +52,15 @@ struct sw_precond {
     double* k3 = nullptr;    // [ncol] sum w K3
     double* work = nullptr;  // [4][NM]
     double* tmp = nullptr;   // workspace of the diagonal-block inversion
-    double* tmp2 = nullptr;  // [q][N][N] products of one factorisation step
+    double* tmp2 = nullptr;  // [2q][N][N] products of one factorisation step
     int* info = nullptr;     // [M] zero pivots seen
     void* terms = nullptr;   // device GemvTerm lists of the band substitution steps
-    hipGraphExec_t subst = nullptr;  // the 2M substitution launches, captured once
+    hipGraphExec_t subst = nullptr;  // the substitution launches, captured once
     std::vector<int> fwd_off, fwd_cnt, bwd_off, bwd_cnt;
+    int sb = 0;                      // block rows per super row (0: one block row per step)
+    double* W = nullptr;             // super-row operators (nonzero N x N blocks)
+    std::vector<sw::SuperStep> fsteps, bsteps;  // kernel arguments of the super-row steps
+    std::vector<int> sl0;                       // first block row of each super row
     size_t bytes = 0;
     int device = -1;
 };
@@ -210,12 +228,17 @@ __global__ __launch_bounds__(256) void k_assemble(Geo g, int q, const double* __
 // which is the Schur complement B - B[:,panel] W B[R,:] on the other rows and
 // W B[R,:] on the pivot rows, i.e. the same as taking the w steps one by one.
 
+// Pivot key of a candidate: the high word of |v|, which orders non-negative doubles
+// (NaN above infinity, so a NaN column is taken and reported).  Values that agree in
+// the high word (20 mantissa bits) tie and the lowest lane wins: partial pivoting
+// needs a large pivot, not the exact maximum.
+__device__ __forceinline__ int pivot_key(double v) {
+    return (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
+}
+
 template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -226,19 +249,28 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 
 // Maximum over each row of 16 lanes, left in every lane of that row
-// (quad swaps, then half-row and row mirrors).  NaN operands are dropped by fmax.
-__device__ __forceinline__ double row16_max_f64(double v) {
-    v = fmax(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_f64<0x141>(v));  // row_half_mirror
-    v = fmax(v, dpp_f64<0x140>(v));  // row_mirror
+// (quad swaps, then half-row and row mirrors).
+__device__ __forceinline__ int row16_max_i32(int v) {
+    v = max(v, dpp_i32<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = max(v, dpp_i32<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = max(v, dpp_i32<0x141>(v));  // row_half_mirror
+    v = max(v, dpp_i32<0x140>(v));  // row_mirror
     return v;
 }
 
-__device__ __forceinline__ double wave_max_f64(double v) {
-    v = row16_max_f64(v);
-    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
-                fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+__device__ __forceinline__ int wave_max_i32(int v) {
+    v = row16_max_i32(v);
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// 1/x: hardware estimate and two Newton steps; 0 and NaN give NaN (counted as a zero pivot)
+__device__ __forceinline__ double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
 }
 
 // ---- N <= 192: the whole block in registers, one workgroup ----
@@ -298,19 +330,17 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 #pragma unroll
             for (int s = 0; s < kPW; ++s) {
                 if (s >= kb) break;
-                double best = -1.0;
-                int bi = -1;
+                int key = -1, bi = -1;
 #pragma unroll
                 for (int i = 0; i < RW; ++i) {
-                    const double v = fabs(pv[i][s]);
-                    if (!((usedm >> i) & 1u) && (bi < 0 || v > best)) {
-                        best = v;
+                    const int kk = pivot_key(pv[i][s]);
+                    if (!((usedm >> i) & 1u) && kk > key) {
+                        key = kk;
                         bi = i;
                     }
                 }
-                const double mx = wave_max_f64(best);
-                unsigned long long mask = __ballot(bi >= 0 && best == mx);
-                if (mask == 0) mask = __ballot(bi >= 0);  // the column holds NaN
+                const int mx = wave_max_i32(key);
+                const unsigned long long mask = __ballot(bi >= 0 && key == mx);
                 const int pl = mask ? __builtin_ctzll(mask) : 0;
                 const int pi = max(0, __builtin_amdgcn_readlane(bi, pl));
                 const int rp = pl + 64 * pi;
@@ -324,7 +354,7 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
                         for (int u = 0; u < kPW; ++u) prow[u] = readlane_f64(pv[i][u], pl);
                 const double piv = prow[s];
                 if (!(fabs(piv) > 0.0)) ++zeros;
-                const double d = 1.0 / piv;
+                const double d = rcp64(piv);
                 double pd[kPW];
 #pragma unroll
                 for (int u = 0; u < kPW; ++u) pd[u] = (u == s) ? d : prow[u] * d;
@@ -356,30 +386,46 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
         }
         __syncthreads();
         // old pivot rows to Zr; their base becomes zero
+        {
+            int st[RB];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r = tr + 16 * i;
-            const int st = step_of[r];
-            if (st >= k0 && st < k0 + kb) {
+            for (int i = 0; i < RB; ++i) st[i] = step_of[tr + 16 * i] - k0;
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    Zr[st - k0][tc + 32 * c] = a[i][c];
-                    a[i][c] = 0.0;
+            for (int i = 0; i < RB; ++i) {
+                if (st[i] >= 0 && st[i] < kb) {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        Zr[st[i]][tc + 32 * c] = a[i][c];
+                        a[i][c] = 0.0;
+                    }
                 }
             }
         }
         __syncthreads();
+        // rank-kb update, operands of step u + 1 loaded while step u is applied
+        {
+            double z[CB], p[RB];
 #pragma unroll
-        for (int u = 0; u < kPW; ++u) {
-            if (u >= kb) break;
-            double z[CB];
+            for (int c = 0; c < CB; ++c) z[c] = Zr[0][tc + 32 * c];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) z[c] = Zr[u][tc + 32 * c];
+            for (int i = 0; i < RB; ++i) p[i] = Pn[tr + 16 * i][0];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const double p = Pn[tr + 16 * i][u];
+            for (int u = 0; u < kPW; ++u) {
+                if (u >= kb) break;
+                double zn[CB], pn[RB];
+                const int un = (u + 1 < kPW) ? u + 1 : u;
 #pragma unroll
-                for (int c = 0; c < CB; ++c) a[i][c] = fma(p, z[c], a[i][c]);
+                for (int c = 0; c < CB; ++c) zn[c] = Zr[un][tc + 32 * c];
+#pragma unroll
+                for (int i = 0; i < RB; ++i) pn[i] = Pn[tr + 16 * i][un];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) a[i][c] = fma(p[i], z[c], a[i][c]);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) z[c] = zn[c];
+#pragma unroll
+                for (int i = 0; i < RB; ++i) p[i] = pn[i];
             }
         }
 #pragma unroll
@@ -404,9 +450,11 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 
 // ---- N > 192: the block in global memory, one panel and one update launch per panel ----
 // Panel kernel: one workgroup per block, thread r holds row r of the panel (N <= 1024).
-// Pivot search: DPP maximum per wavefront, then over the 16 wavefront candidates.
+// One block barrier per step: every wavefront posts its best candidate (key, row,
+// and the row already scaled by the candidate's reciprocal) in a double-buffered
+// LDS slot; after the barrier every thread takes the best of the 16 posts.
 // It writes the new panel columns pn[N][kPWG], the old pivot rows z[kPWG][N],
-// step_of[N] and rowpiv[N] (per block, in the workspace gjw).
+// step_of[N] and rowpiv[N] (per block, in the workspace).
 constexpr int kGP = 1024;
 constexpr int kPWG = 16;
 
@@ -424,8 +472,8 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     double* z = w.z + (size_t)blockIdx.x * kPWG * N;
     int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
     int* rowpiv = step_of + N;
-    __shared__ double candv[16], prow[kPWG];
-    __shared__ int candr[16], rp_s[kPWG];
+    __shared__ double rec[2][16][kPWG + 1];  // scaled candidate row, then its pivot value
+    __shared__ int ckey[2][16], crow[2][16], rp_s[kPWG];
     const int r = threadIdx.x, lane = r & 63, wv = r >> 6;
     const int kb = min(kPWG, N - k0);
     const bool valid = r < N;
@@ -438,33 +486,32 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
 #pragma unroll
     for (int s = 0; s < kPWG; ++s) {
         if (s >= kb) break;
+        const int buf = s & 1;
         const bool cand = valid && st < 0;
-        const double v = cand ? fabs(pv[s]) : -1.0;
-        const double wm = wave_max_f64(v);
-        unsigned long long mask = __ballot(cand && v == wm);
-        if (mask == 0) mask = __ballot(cand);
+        const int key = cand ? pivot_key(pv[s]) : -1;
+        const int wm = wave_max_i32(key);
+        const unsigned long long mask = __ballot(cand && key == wm);
+        const int wl = mask ? __builtin_ctzll(mask) : -1;
+        if (lane == wl) {
+            const double d = rcp64(pv[s]);
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) rec[buf][wv][u] = (u == s) ? d : pv[u] * d;
+            rec[buf][wv][kPWG] = pv[s];
+        }
         if (lane == 0) {
-            candv[wv] = mask ? wm : -2.0;
-            candr[wv] = mask ? (wv * 64 + __builtin_ctzll(mask)) : -1;
+            ckey[buf][wv] = mask ? wm : -1;
+            crow[buf][wv] = mask ? wv * 64 + wl : -1;
         }
         __syncthreads();
-        const double cv = (lane < 16) ? candv[lane] : -2.0;
-        const int cr = (lane < 16) ? candr[lane] : -1;
-        const double gm = readlane_f64(row16_max_f64(cv), 0);
-        unsigned long long m2 = __ballot(cr >= 0 && cv == gm);
-        if (m2 == 0) m2 = __ballot(cr >= 0);
-        const int rp = m2 ? __builtin_amdgcn_readlane(cr, __builtin_ctzll(m2)) : 0;
-        if (r == rp)
-#pragma unroll
-            for (int u = 0; u < kPWG; ++u) prow[u] = pv[u];
-        __syncthreads();
+        const int ck = (lane < 16) ? ckey[buf][lane] : -1;
+        const int gm = __builtin_amdgcn_readlane(row16_max_i32(ck), 0);
+        const unsigned long long m2 = __ballot(lane < 16 && ck >= 0 && ck == gm);
+        const int ww = m2 ? __builtin_ctzll(m2) : 0;
+        const int rp = max(0, min(N - 1, crow[buf][ww]));
         double pd[kPWG];
 #pragma unroll
-        for (int u = 0; u < kPWG; ++u) pd[u] = prow[u];
-        const double piv = pd[s];
-        const double d = 1.0 / piv;
-#pragma unroll
-        for (int u = 0; u < kPWG; ++u) pd[u] = (u == s) ? d : pd[u] * d;
+        for (int u = 0; u < kPWG; ++u) pd[u] = rec[buf][ww][u];
+        const double d = pd[s];
         if (r == rp) {
 #pragma unroll
             for (int u = 0; u < kPWG; ++u) pv[u] = pd[u];
@@ -477,7 +524,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         if (r == 0) {
             rp_s[s] = rp;
             rowpiv[k0 + s] = rp;
-            if (!(fabs(piv) > 0.0)) ++zeros;
+            if (!(fabs(rec[buf][ww][kPWG]) > 0.0)) ++zeros;
         }
     }
     if (valid) {
@@ -608,60 +655,81 @@ struct GemmBatch {
     GemmJob j[kMaxGemmJobs];
 };
 
+// FP64 matrix cores (v_mfma_f64_16x16x4f64): a 64 x 64 tile of C per workgroup,
+// 32 x 32 (2 x 2 MFMA tiles) per wavefront, K staged through LDS 16 at a time with
+// the next slice prefetched into registers.  Operand layout of the instruction:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane
+// l is C[l / 16 + 4 r][l % 16].
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kGK = 16;
+
 __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch batch) {
     const GemmJob job = batch.j[blockIdx.z];
     const double* __restrict__ A = job.A;
     const double* __restrict__ B = job.B;
+    __shared__ double As[64][kGK + 1];
+    __shared__ double Bs[kGK][64 + 2];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int ar = t >> 2, ak = (t & 3) * 4;   // A slice 64 x 16: row ar, k ak..ak+3
+    const int bk = t >> 4, bc = (t & 15) * 4;  // B slice 16 x 64: k bk, cols bc..bc+3
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int gr = row0 + ar, gk = k0 + ak + e;
+            ra[e] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : 0.0;
+            const int gk2 = k0 + bk, gc = col0 + bc + e;
+            rb[e] = (gk2 < n && gc < n) ? B[(size_t)gk2 * n + gc] : 0.0;
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            As[ar][ak + e] = ra[e];
+            Bs[bk][bc + e] = rb[e];
+        }
+        __syncthreads();
+        if (k0 + kGK < n) load(k0 + kGK);
+#pragma unroll
+        for (int k4 = 0; k4 < kGK; k4 += 4) {
+            double fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = As[wr + a * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = Bs[k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+    }
     const double* Cin = job.Cin;
     double* C = job.C;
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][64];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-            const int r = e / 16, kk = e % 16;
-            const int gr = row0 + r, gk = k0 + kk;
-            As[kk][r] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : 0.0;
-        }
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e / 64, c = e % 64;
-            const int gk = k0 + kk, gc = col0 + c;
-            Bs[kk][c] = (gk < n && gc < n) ? B[(size_t)gk * n + gc] : 0.0;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = row0 + ty * 4 + i, c = col0 + tx * 4 + j;
-            if (r < n && c < n) {
-                const size_t o = (size_t)r * n + c;
-                C[o] = (Cin ? Cin[o] : 0.0) + alpha * acc[i][j];
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wr + a * 16 + (lane >> 4) + 4 * r;
+                const int gc = col0 + wc + b * 16 + (lane & 15);
+                if (gr < n && gc < n) {
+                    const size_t o = (size_t)gr * n + gc;
+                    C[o] = (Cin ? Cin[o] : 0.0) + alpha * acc[a][b][r];
+                }
             }
-        }
 }
 
-__global__ void k_copy(size_t n, const double* __restrict__ a, double* __restrict__ b) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (size_t)gridDim.x * blockDim.x)
-        b[t] = a[t];
-}
 
 // ---- apply ----------------------------------------------------------------------------
 // One 64-lane workgroup per row l; the row lives in LDS.  Both sequential
@@ -803,6 +871,71 @@ __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const doub
     if (lane == 0) x[wid] = p;
 }
 
+// One wavefront per output row of a super-row step (SuperStep); four terms'
+// loads are issued together.
+__global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st,
+                                                    double* __restrict__ out) {
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wid >= st.nrow * N) return;
+    const int i = wid / N, r = wid - i * N;
+    const int t0 = st.first[i], t1 = st.first[i + 1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+        const double* b0 = st.blk[t] + (size_t)r * N;
+        const double* b1 = st.blk[t + 1] + (size_t)r * N;
+        const double* b2 = st.blk[t + 2] + (size_t)r * N;
+        const double* b3 = st.blk[t + 3] + (size_t)r * N;
+        const double* v0 = st.vec[t];
+        const double* v1 = st.vec[t + 1];
+        const double* v2 = st.vec[t + 2];
+        const double* v3 = st.vec[t + 3];
+        for (int n = lane; n < N; n += 64) {
+            s0 = fma(b0[n], v0[n], s0);
+            s1 = fma(b1[n], v1[n], s1);
+            s2 = fma(b2[n], v2[n], s2);
+            s3 = fma(b3[n], v3[n], s3);
+        }
+    }
+    for (; t < t1; ++t) {
+        const double* b0 = st.blk[t] + (size_t)r * N;
+        const double* v0 = st.vec[t];
+        for (int n = lane; n < N; n += 64) s0 = fma(b0[n], v0[n], s0);
+    }
+    double sum = (s0 + s1) + (s2 + s3);
+    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+    if (lane == 0) out[wid] = sum;
+}
+
+// dst = 0, I, src or -src for a batch of N x N blocks; grid (chunks, jobs)
+struct FillJob {
+    double* dst;
+    const double* src;
+    int mode;  // 0 zero, 1 identity, 2 copy, 3 negated copy
+    int pad;
+};
+struct FillBatch {
+    FillJob j[64];
+};
+__global__ void k_fill_blocks(int N, FillBatch b) {
+    const FillJob job = b.j[blockIdx.y];
+    const size_t NN = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < NN;
+         e += (size_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (job.mode == 1) {
+            const size_t r = e / N;
+            v = (e - r * N == r) ? 1.0 : 0.0;
+        } else if (job.mode == 2) {
+            v = job.src[e];
+        } else if (job.mode == 3) {
+            v = -job.src[e];
+        }
+        job.dst[e] = v;
+    }
+}
+
 size_t blk_off(const sw_precond* P, int l, int slot) {
     return ((size_t)l * P->nb + slot) * (size_t)P->g.N * P->g.N;
 }
@@ -817,16 +950,13 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
     }
 }
 
-void copy(size_t n, const double* a, double* b, hipStream_t s) {
-    k_copy<<<(unsigned)std::min<size_t>((n + 255) / 256, 8192), 256, 0, s>>>(n, a, b);
-}
 
 }  // namespace
 
 namespace {
 // scratch blocks: q products per factorisation step, or M inverses at once (q = 0, N > 192)
 size_t tmp2_blocks(const Geo& g, int q) {
-    return (size_t)std::max({q, 1, (q == 0 && g.N > 192) ? g.M : 1});
+    return (size_t)std::max({2 * q, 1, (q == 0 && g.N > 192) ? g.M : 1});
 }
 
 // workspace of the diagonal-block inversion (N > 192), at least one N x N block
@@ -841,14 +971,219 @@ int k3_chunks(const Geo& g) {
 }
 }  // namespace
 
+// ---- super-row substitution -----------------------------------------------------------
+// The block substitutions are regrouped into super rows of b block rows.  Forward
+// (L unit block-lower with band q): the blocks y_L of one super row satisfy
+//     A_L y_L = t_L - C_L y_prev,   A_L = I + (L inside the super row),
+// so y_L = W_L [y_prev; t_L] with W_L = A_L^{-1} [-C_L | I].  Backward (x_l = Dinv_l y_l
+// - sum_d G_{l,l+d} x_{l+d}): x_L = W'_L [y_L; x_next], W'_L = B_L^{-1} [Dg_L | -C'_L],
+// B_L = I + (G inside the super row).  W and W' are formed once by block substitution
+// on their right-hand sides (GEMMs), keeping only the nonzero blocks, and each
+// application then takes 2 ceil(M/b) launches instead of 2M.
+namespace {
+constexpr double kSuperTarget = 1000.0;  // b N: super-row height in grid rows
+
+struct SuperRow {
+    int l0 = 0, nb = 0, nprev = 0;   // first block row, block rows, coupled outside blocks
+    std::vector<std::vector<int>> id;  // [nb][nb + nprev]: operator block index or -1
+};
+struct SuperPlan {
+    int b = 0;
+    std::vector<SuperRow> fwd, bwd;
+    size_t nblocks = 0;
+};
+
+int super_rows(const Geo& g, int q) {
+    if (q == 0) return 0;
+    int b = (int)std::lround(kSuperTarget / g.N);
+    b = std::min({b, g.M, kMaxSuperRows});
+    // every block row couples to at most q outside and b inside blocks
+    while (b > 1 && b * (b + q) > kMaxSuperTerms) --b;
+    return b > 1 ? b : 0;
+}
+
+// Nonzero block pattern of W (forward) and W' (backward).  Forward input blocks are
+// [y_{l0-nprev} .. y_{l0-1}, t_{l0} .. t_{l0+nb-1}]; backward [y_{l0} .. y_{l0+nb-1},
+// x_{l0+nb} .. x_{l0+nb+nprev-1}].
+SuperPlan plan_super(const Geo& g, int q, int b) {
+    SuperPlan P;
+    P.b = b;
+    if (b <= 1) return P;
+    size_t next = 0;
+    for (int l0 = 0; l0 < g.M; l0 += b) {
+        const int nb = std::min(b, g.M - l0);
+        {  // forward
+            SuperRow R;
+            R.l0 = l0;
+            R.nb = nb;
+            R.nprev = std::min(q, l0);
+            const int nin = nb + R.nprev, nq = R.nprev;
+            std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
+            for (int i = 0; i < nb; ++i) {
+                for (int c = 0; c < nq; ++c) nz[i][c] = (i + nq - c >= 1 && i + nq - c <= q);
+                nz[i][nq + i] = 1;
+                for (int d = 1; d <= std::min(q, i); ++d)
+                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[i - d][c];
+            }
+            R.id.assign(nb, std::vector<int>(nin, -1));
+            for (int i = 0; i < nb; ++i)
+                for (int c = 0; c < nin; ++c)
+                    if (nz[i][c]) R.id[i][c] = (int)next++;
+            P.fwd.push_back(std::move(R));
+        }
+        {  // backward
+            SuperRow R;
+            R.l0 = l0;
+            R.nb = nb;
+            R.nprev = std::min(q, g.M - (l0 + nb));
+            const int nin = nb + R.nprev;
+            std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
+            for (int i = nb - 1; i >= 0; --i) {
+                nz[i][i] = 1;
+                for (int c = nb; c < nin; ++c) nz[i][c] = (c - i >= 1 && c - i <= q);
+                for (int d = 1; d <= std::min(q, nb - 1 - i); ++d)
+                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[i + d][c];
+            }
+            R.id.assign(nb, std::vector<int>(nin, -1));
+            for (int i = 0; i < nb; ++i)
+                for (int c = 0; c < nin; ++c)
+                    if (nz[i][c]) R.id[i][c] = (int)next++;
+            P.bwd.push_back(std::move(R));
+        }
+    }
+    P.nblocks = next;
+    return P;
+}
+
+void fill_batched(int N, const std::vector<FillJob>& jobs, hipStream_t s) {
+    const size_t NN = (size_t)N * N;
+    const unsigned gx = (unsigned)std::min<size_t>((NN + 255) / 256, 64);
+    for (size_t b = 0; b < jobs.size(); b += 64) {
+        FillBatch fb{};
+        const int cnt = (int)std::min<size_t>(64, jobs.size() - b);
+        for (int i = 0; i < cnt; ++i) fb.j[i] = jobs[b + i];
+        k_fill_blocks<<<dim3(gx, cnt), 256, 0, s>>>(N, fb);
+    }
+}
+
+// Form W and W' from the band factors in P->S and record the step arguments.
+void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
+    const Geo& g = P->g;
+    const int q = P->q, N = g.N;
+    const size_t NN = (size_t)N * N, NM = g.NM;
+    auto Wb = [&](int id) { return P->W + (size_t)id * NN; };
+    auto Sb = [&](int l, int slot) { return P->S + blk_off(P, l, slot); };
+    std::vector<FillJob> fills;
+    for (const SuperRow& R : plan.fwd) {
+        const int nq = R.nprev;
+        for (int i = 0; i < R.nb; ++i)
+            for (int c = 0; c < R.nb + nq; ++c) {
+                if (R.id[i][c] < 0) continue;
+                FillJob j{Wb(R.id[i][c]), nullptr, 0, 0};
+                if (c < nq && i + nq - c >= 1 && i + nq - c <= q) {
+                    j.src = Sb(R.l0 + i, q - (i + nq - c));  // L_{l, l-d}, d = i + nq - c
+                    j.mode = 3;
+                } else if (c == nq + i) {
+                    j.mode = 1;
+                }
+                fills.push_back(j);
+            }
+    }
+    for (const SuperRow& R : plan.bwd) {
+        for (int i = 0; i < R.nb; ++i)
+            for (int c = 0; c < R.nb + R.nprev; ++c) {
+                if (R.id[i][c] < 0) continue;
+                FillJob j{Wb(R.id[i][c]), nullptr, 0, 0};
+                if (c == i) {
+                    j.src = Sb(R.l0 + i, q);  // Dinv_l
+                    j.mode = 2;
+                } else if (c >= R.nb && c - i >= 1 && c - i <= q) {
+                    j.src = Sb(R.l0 + i, q + (c - i));  // G_{l, l+d}, d = c - i
+                    j.mode = 3;
+                }
+                fills.push_back(j);
+            }
+    }
+    fill_batched(N, fills, s);
+    // forward levels: W_i -= L_{l0+i, l0+i-d} W_{i-d}
+    for (int i = 1; i < plan.b; ++i)
+        for (int d = 1; d <= std::min(q, i); ++d) {
+            std::vector<GemmJob> jobs;
+            for (const SuperRow& R : plan.fwd) {
+                if (i >= R.nb) continue;
+                for (int c = 0; c < R.nb + R.nprev; ++c) {
+                    const int src = R.id[i - d][c];
+                    if (src < 0) continue;
+                    double* dst = Wb(R.id[i][c]);
+                    jobs.push_back(GemmJob{Sb(R.l0 + i, q - d), Wb(src), dst, dst});
+                }
+            }
+            gemm_batched(N, -1.0, jobs, s);
+        }
+    // backward levels (e = nb - 1 - i): W'_i -= G_{l0+i, l0+i+d} W'_{i+d}
+    for (int e = 1; e < plan.b; ++e)
+        for (int d = 1; d <= std::min(q, e); ++d) {
+            std::vector<GemmJob> jobs;
+            for (const SuperRow& R : plan.bwd) {
+                const int i = R.nb - 1 - e;
+                if (i < 0) continue;
+                for (int c = 0; c < R.nb + R.nprev; ++c) {
+                    const int src = R.id[i + d][c];
+                    if (src < 0) continue;
+                    double* dst = Wb(R.id[i][c]);
+                    jobs.push_back(GemmJob{Sb(R.l0 + i, q + d), Wb(src), dst, dst});
+                }
+            }
+            gemm_batched(N, -1.0, jobs, s);
+        }
+    // step arguments: forward inputs y (= work + 3 NM) and t2 (= work + NM); backward
+    // inputs y and x (= work + 2 NM)
+    const double* t2 = P->work + NM;
+    const double* xv = P->work + 2 * NM;
+    const double* yv = P->work + 3 * NM;
+    auto make = [&](const SuperRow& R, bool fwd) {
+        SuperStep st{};
+        st.nrow = R.nb;
+        int t = 0;
+        for (int i = 0; i < R.nb; ++i) {
+            st.first[i] = t;
+            for (int c = 0; c < R.nb + R.nprev; ++c) {
+                if (R.id[i][c] < 0) continue;
+                const double* v;
+                if (fwd)
+                    v = (c < R.nprev) ? yv + (size_t)(R.l0 - R.nprev + c) * N
+                                      : t2 + (size_t)(R.l0 + c - R.nprev) * N;
+                else
+                    v = (c < R.nb) ? yv + (size_t)(R.l0 + c) * N : xv + (size_t)(R.l0 + c) * N;
+                if (t >= kMaxSuperTerms) throw Error{SW_EINVAL, "super-row step has too many terms"};
+                st.blk[t] = Wb(R.id[i][c]);
+                st.vec[t] = v;
+                ++t;
+            }
+        }
+        st.first[R.nb] = t;
+        return st;
+    };
+    P->fsteps.clear();
+    P->bsteps.clear();
+    P->sl0.clear();
+    for (const SuperRow& R : plan.fwd) {
+        P->fsteps.push_back(make(R, true));
+        P->sl0.push_back(R.l0);
+    }
+    for (const SuperRow& R : plan.bwd) P->bsteps.push_back(make(R, false));
+}
+}  // namespace
+
 size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const int q = std::max(0, std::min(q_req, g.M - 1));
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
     const int G = k3_chunks(g);
+    const size_t nw = plan_super(g, q, super_rows(g, q)).nblocks;
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
-                       gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4, (size_t)G * g.ncol * 8,
-                       NN * 8});
+                       gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4,
+                       (size_t)G * g.ncol * 8, NN * 8, nw * NN * 8});
 }
 
 size_t precond_bytes(const sw_precond* P) { return P ? P->bytes : 0; }
@@ -894,6 +1229,9 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->info = c.take<int>(g.M);
     double* part = c.take<double>((size_t)G * g.ncol);
     double* X = c.take<double>(NN);
+    const SuperPlan plan = plan_super(g, q, super_rows(g, q));
+    P->sb = plan.b;
+    P->W = c.take<double>(plan.nblocks * NN);
     try {
         k_wmat<<<(g.N + 63) / 64, 64, 0, s>>>(g, X, P->Wc);
         const int ntile = (g.ncol + 255) / 256;
@@ -905,44 +1243,47 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         if (q == 0) {
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
         } else {
-            double* scratchL = P->tmp2;  // q blocks for L_{i,l} and G_{l,j}
+            double* scratchL = P->tmp2;  // 2q blocks: L_{i,l}, then G_{l,j}
             for (int l = 0; l < g.M; ++l) {
                 gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, P->tmp2, P->tmp,
                            s);
                 const int hi = std::min(g.M - 1, l + q);
                 const int cnt = hi - l;
                 if (cnt == 0) continue;
+                // L_{i,l} = S_{i,l} Dinv_l and G_{l,j} = Dinv_l U_{l,j} into scratch
                 std::vector<GemmJob> jobs;
-                // L_{i,l} = S_{i,l} Dinv_l (into scratch, then copied back)
                 for (int i = l + 1; i <= hi; ++i)
                     jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
                                            P->S + blk_off(P, l, q), nullptr,
                                            scratchL + (size_t)(i - l - 1) * NN});
+                for (int j = l + 1; j <= hi; ++j)
+                    jobs.push_back(GemmJob{P->S + blk_off(P, l, q), P->S + blk_off(P, l, j - l + q),
+                                           nullptr, scratchL + (size_t)(q + j - l - 1) * NN});
                 gemm_batched(g.N, 1.0, jobs, s);
-                for (int i = l + 1; i <= hi; ++i)
-                    copy(NN, scratchL + (size_t)(i - l - 1) * NN, P->S + blk_off(P, i, l - i + q),
-                         s);
                 // S_{i,j} -= L_{i,l} U_{l,j}
                 jobs.clear();
                 for (int i = l + 1; i <= hi; ++i)
                     for (int j = l + 1; j <= hi; ++j) {
                         double* Sij = P->S + blk_off(P, i, j - i + q);
-                        jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
+                        jobs.push_back(GemmJob{scratchL + (size_t)(i - l - 1) * NN,
                                                P->S + blk_off(P, l, j - l + q), Sij, Sij});
                     }
                 gemm_batched(g.N, -1.0, jobs, s);
-                // G_{l,j} = Dinv_l U_{l,j}
-                jobs.clear();
+                // L and G replace S_{i,l} and U_{l,j}
+                std::vector<FillJob> back;
+                for (int i = l + 1; i <= hi; ++i)
+                    back.push_back(FillJob{P->S + blk_off(P, i, l - i + q),
+                                           scratchL + (size_t)(i - l - 1) * NN, 2, 0});
                 for (int j = l + 1; j <= hi; ++j)
-                    jobs.push_back(GemmJob{P->S + blk_off(P, l, q), P->S + blk_off(P, l, j - l + q),
-                                           nullptr, scratchL + (size_t)(j - l - 1) * NN});
-                gemm_batched(g.N, 1.0, jobs, s);
-                for (int j = l + 1; j <= hi; ++j)
-                    copy(NN, scratchL + (size_t)(j - l - 1) * NN, P->S + blk_off(P, l, j - l + q),
-                         s);
+                    back.push_back(FillJob{P->S + blk_off(P, l, j - l + q),
+                                           scratchL + (size_t)(q + j - l - 1) * NN, 2, 0});
+                fill_batched(g.N, back, s);
             }
         }
-        if (q > 0) {
+        if (q > 0 && P->sb > 1) {
+            build_super(P, plan, s);
+            capture_substitution(P);
+        } else if (q > 0) {
             std::vector<GemvTerm> tv;
             double* tmpv = P->work + 3 * NM;
             double* xv = P->work + 2 * NM;
@@ -997,6 +1338,20 @@ void enqueue_substitution(const sw_precond* P, hipStream_t s) {
     double* t2 = P->work + NM;
     double* s2 = P->work + 2 * NM;
     double* tmp = P->work + 3 * NM;
+    if (P->sb > 1) {
+        // y in tmp, x in s2 (the step arguments point there)
+        for (size_t k = 0; k < P->fsteps.size(); ++k) {
+            const SuperStep& st = P->fsteps[k];
+            k_super_step<<<(unsigned)((st.nrow * N * 64 + 255) / 256), 256, 0, s>>>(
+                N, st, tmp + (size_t)P->sl0[k] * N);
+        }
+        for (size_t k = P->bsteps.size(); k-- > 0;) {
+            const SuperStep& st = P->bsteps[k];
+            k_super_step<<<(unsigned)((st.nrow * N * 64 + 255) / 256), 256, 0, s>>>(
+                N, st, s2 + (size_t)P->sl0[k] * N);
+        }
+        return;
+    }
     const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);
     const unsigned blocks = (unsigned)((N * 64 + 255) / 256);
     // forward: y_l = t_l - sum_d L_{l,l-d} y_{l-d}   (y in tmp)

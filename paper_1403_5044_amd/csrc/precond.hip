@@ -274,122 +274,143 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 // ---- N <= 192: the whole block in registers, one workgroup ----
-// Thread (tr = t / 32, tc = t % 32) holds B[tr + 16 i][tc + 32 c].  Wavefront 0
-// eliminates each panel of kPW columns with rows lane + 64 i in registers (pivot
-// search by DPP and readlane, no block barrier); all threads then apply the
-// rank-kPW update from LDS.
+// Wavefront 0 eliminates the panels (rows lane + 64 i in registers; pivot search by
+// DPP and readlane, no block barrier).  Wavefronts 1..7 hold the block: thread
+// (tr = t' / 32, tc = t' % 32), t' = t - 64, holds B[tr + 14 i][tc + 32 c].  Look-ahead:
+// the owners stage panel k+1's columns in LDS, all tile threads apply panel k to them
+// (one row each), and wavefront 0 eliminates panel k+1 while the others apply panel
+// k's rank-kPW update to the whole block.
 constexpr int kGT = 512;
 constexpr int kPW = 8;
 
-template <int RB, int CB>
+// Eliminates the panel held in pv (rows lane + 64 i, columns k0 .. k0 + kb - 1) in place.
+template <int RW>
+__device__ __forceinline__ void gj_panel_wave(int k0, int kb, int lane, double (&pv)[RW][kPW],
+                                              int* rowpiv, int* step_of, unsigned& usedm,
+                                              int& zeros) {
+#pragma unroll
+    for (int s = 0; s < kPW; ++s) {
+        if (s >= kb) break;
+        int key = -1, bi = -1;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int kk = pivot_key(pv[i][s]);
+            if (!((usedm >> i) & 1u) && kk > key) {
+                key = kk;
+                bi = i;
+            }
+        }
+        const int mx = wave_max_i32(key);
+        const unsigned long long mask = __ballot(bi >= 0 && key == mx);
+        const int pl = mask ? __builtin_ctzll(mask) : 0;
+        const int pi = max(0, __builtin_amdgcn_readlane(bi, pl));
+        const int rp = pl + 64 * pi;
+        double prow[kPW];
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) prow[u] = 0.0;
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+            if (i == pi)
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) prow[u] = readlane_f64(pv[i][u], pl);
+        const double piv = prow[s];
+        if (!(fabs(piv) > 0.0)) ++zeros;
+        const double d = rcp64(piv);
+        double pd[kPW];
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) pd[u] = (u == s) ? d : prow[u] * d;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const double m = pv[i][s];
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
+        }
+        if (lane == pl) {
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+                if (i == pi) {
+#pragma unroll
+                    for (int u = 0; u < kPW; ++u) pv[i][u] = pd[u];
+                    usedm |= 1u << i;
+                }
+        }
+        if (lane == 0) {
+            rowpiv[k0 + s] = rp;
+            step_of[rp] = k0 + s;
+        }
+    }
+}
+
+// RB x CB block per tile thread (14 RB >= N, 32 CB >= N), RW panel rows per lane (64 RW >= N)
+template <int RB, int CB, int RW>
 __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ base, size_t stride,
                                                  int* __restrict__ info) {
-    constexpr int R = 16 * RB, C = 32 * CB, RW = R / 64;
-    static_assert(R == C && RW * 64 == R, "square tile, whole rows per lane of one wave");
+    constexpr int R = 14 * RB, C = 32 * CB;
+    constexpr int RP = (R > 64 * RW) ? R : 64 * RW;  // rows of the panel buffers
     double* A = base + (size_t)blockIdx.x * stride;
-    __shared__ double Pn[R][kPW];
-    __shared__ double Zr[kPW][C];
-    __shared__ int rowpiv[C], step_of[R];
+    __shared__ double Pn[2][RP][kPW];  // eliminated panels k (k even / odd)
+    __shared__ double Pin[RP][kPW];    // panel columns staged for elimination
+    __shared__ double Zr[kPW][C];      // pivot rows before the update
+    __shared__ int rowpiv[C], step_of[RP];
     const int t = threadIdx.x;
-    const int tc = t & 31, tr = t >> 5, lane = t & 63;
+    const int lane = t & 63;
     const bool w0 = t < 64;
+    const int tt = t - 64;  // tile thread
+    const int tc = tt & 31, tr = tt >> 5;
     double a[RB][CB];
+    if (!w0) {
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int r = tr + 16 * i, j = tc + 32 * c;
-            a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
-        }
-    for (int r = t; r < R; r += kGT) {
-        step_of[r] = -1;
-        rowpiv[r] = -1;
+            for (int c = 0; c < CB; ++c) {
+                const int r = tr + 14 * i, j = tc + 32 * c;
+                a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
+            }
     }
+    for (int e = t; e < RP * kPW; e += kGT) {
+        (&Pn[0][0][0])[e] = 0.0;
+        (&Pn[1][0][0])[e] = 0.0;
+        (&Pin[0][0])[e] = 0.0;
+    }
+    for (int r = t; r < RP; r += kGT) step_of[r] = -1;
+    for (int r = t; r < C; r += kGT) rowpiv[r] = -1;
     unsigned usedm = 0;  // wavefront 0: bit i marks row lane + 64 i as pivoted or padding
 #pragma unroll
     for (int i = 0; i < RW; ++i)
         if (lane + 64 * i >= N) usedm |= 1u << i;
     int zeros = 0;
     __syncthreads();
-    for (int k0 = 0; k0 < N; k0 += kPW) {
-        const int kb = min(kPW, N - k0);
+    // panel 0 columns
+    if (!w0 && tc < kPW) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc] = a[i][0];
+    }
+    __syncthreads();
+    if (w0) {
+        double pv[RW][kPW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) pv[i][u] = Pin[lane + 64 * i][u];
+        gj_panel_wave<RW>(0, min(kPW, N), lane, pv, rowpiv, step_of, usedm, zeros);
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) Pn[0][lane + 64 * i][u] = pv[i][u];
+    }
+    __syncthreads();
+    const int npan = (N + kPW - 1) / kPW;
+    for (int k = 0; k < npan; ++k) {
+        const int k0 = k * kPW, kb = min(kPW, N - k0);
+        const int buf = k & 1;
         const int c0 = k0 >> 5, t0 = k0 & 31;  // kPW divides 32: a panel never straddles c
-        const bool pcol = tc >= t0 && tc < t0 + kPW;
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            if (c == c0 && pcol)
-#pragma unroll
-                for (int i = 0; i < RB; ++i) Pn[tr + 16 * i][tc - t0] = a[i][c];
-        __syncthreads();
-        if (w0) {
-            double pv[RW][kPW];
-#pragma unroll
-            for (int i = 0; i < RW; ++i)
-#pragma unroll
-                for (int u = 0; u < kPW; ++u) pv[i][u] = Pn[lane + 64 * i][u];
-#pragma unroll
-            for (int s = 0; s < kPW; ++s) {
-                if (s >= kb) break;
-                int key = -1, bi = -1;
-#pragma unroll
-                for (int i = 0; i < RW; ++i) {
-                    const int kk = pivot_key(pv[i][s]);
-                    if (!((usedm >> i) & 1u) && kk > key) {
-                        key = kk;
-                        bi = i;
-                    }
-                }
-                const int mx = wave_max_i32(key);
-                const unsigned long long mask = __ballot(bi >= 0 && key == mx);
-                const int pl = mask ? __builtin_ctzll(mask) : 0;
-                const int pi = max(0, __builtin_amdgcn_readlane(bi, pl));
-                const int rp = pl + 64 * pi;
-                double prow[kPW];
-#pragma unroll
-                for (int u = 0; u < kPW; ++u) prow[u] = 0.0;
-#pragma unroll
-                for (int i = 0; i < RW; ++i)
-                    if (i == pi)
-#pragma unroll
-                        for (int u = 0; u < kPW; ++u) prow[u] = readlane_f64(pv[i][u], pl);
-                const double piv = prow[s];
-                if (!(fabs(piv) > 0.0)) ++zeros;
-                const double d = rcp64(piv);
-                double pd[kPW];
-#pragma unroll
-                for (int u = 0; u < kPW; ++u) pd[u] = (u == s) ? d : prow[u] * d;
-#pragma unroll
-                for (int i = 0; i < RW; ++i) {
-                    const double m = pv[i][s];
-#pragma unroll
-                    for (int u = 0; u < kPW; ++u)
-                        pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
-                }
-                if (lane == pl) {
-#pragma unroll
-                    for (int i = 0; i < RW; ++i)
-                        if (i == pi) {
-#pragma unroll
-                            for (int u = 0; u < kPW; ++u) pv[i][u] = pd[u];
-                            usedm |= 1u << i;
-                        }
-                }
-                if (lane == 0) {
-                    rowpiv[k0 + s] = rp;
-                    step_of[rp] = k0 + s;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < RW; ++i)
-#pragma unroll
-                for (int u = 0; u < kPW; ++u) Pn[lane + 64 * i][u] = pv[i][u];
-        }
-        __syncthreads();
-        // old pivot rows to Zr; their base becomes zero
-        {
+        const int k1 = k0 + kPW, kb1 = min(kPW, N - k1);
+        const int c1 = k1 >> 5, t1 = k1 & 31;
+        if (!w0) {
+            // pivot rows of panel k to Zr; their base becomes zero
             int st[RB];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) st[i] = step_of[tr + 16 * i] - k0;
+            for (int i = 0; i < RB; ++i) st[i] = step_of[tr + 14 * i] - k0;
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 if (st[i] >= 0 && st[i] < kb) {
@@ -400,15 +421,55 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
                     }
                 }
             }
+            // panel k+1's columns as they stand before panel k's update
+            if (k + 1 < npan && tc >= t1 && tc < t1 + kPW) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c == c1)
+#pragma unroll
+                        for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc - t1] = a[i][c];
+            }
         }
         __syncthreads();
-        // rank-kb update, operands of step u + 1 loaded while step u is applied
-        {
+        if (!w0 && k + 1 < npan && tt < RP) {
+            // panel k applied to the staged columns, one row per thread
+            double pr[kPW], v[kPW];
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) {
+                pr[u] = Pn[buf][tt][u];
+                v[u] = Pin[tt][u];
+            }
+#pragma unroll
+            for (int tt2 = 0; tt2 < kPW; ++tt2) {
+                if (tt2 >= kb) break;
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) v[u] = fma(pr[tt2], Zr[tt2][k1 + u], v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) Pin[tt][u] = v[u];
+        }
+        __syncthreads();
+        if (w0) {
+            if (k + 1 < npan) {
+                // panel k+1 eliminated
+                double pv[RW][kPW];
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int u = 0; u < kPW; ++u) pv[i][u] = Pin[lane + 64 * i][u];
+                gj_panel_wave<RW>(k1, kb1, lane, pv, rowpiv, step_of, usedm, zeros);
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int u = 0; u < kPW; ++u) Pn[buf ^ 1][lane + 64 * i][u] = pv[i][u];
+            }
+        } else {
+            // rank-kb update of the whole block, operands of step u + 1 loaded while u is applied
             double z[CB], p[RB];
 #pragma unroll
             for (int c = 0; c < CB; ++c) z[c] = Zr[0][tc + 32 * c];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) p[i] = Pn[tr + 16 * i][0];
+            for (int i = 0; i < RB; ++i) p[i] = Pn[buf][tr + 14 * i][0];
 #pragma unroll
             for (int u = 0; u < kPW; ++u) {
                 if (u >= kb) break;
@@ -417,7 +478,7 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 #pragma unroll
                 for (int c = 0; c < CB; ++c) zn[c] = Zr[un][tc + 32 * c];
 #pragma unroll
-                for (int i = 0; i < RB; ++i) pn[i] = Pn[tr + 16 * i][un];
+                for (int i = 0; i < RB; ++i) pn[i] = Pn[buf][tr + 14 * i][un];
 #pragma unroll
                 for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -427,24 +488,29 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 #pragma unroll
                 for (int i = 0; i < RB; ++i) p[i] = pn[i];
             }
-        }
+            // the panel's own columns take the eliminated values
+            if (tc >= t0 && tc < t0 + kPW) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c)
-            if (c == c0 && pcol)
+                for (int c = 0; c < CB; ++c)
+                    if (c == c0)
 #pragma unroll
-                for (int i = 0; i < RB; ++i) a[i][c] = Pn[tr + 16 * i][tc - t0];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int r = tr + 16 * i, j = tc + 32 * c;
-            if (r < N && j < N) {
-                const int sr = step_of[r], pj = rowpiv[j];
-                if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
+                        for (int i = 0; i < RB; ++i) a[i][c] = Pn[buf][tr + 14 * i][tc - t0];
             }
         }
+        __syncthreads();
+    }
+    if (!w0) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int r = tr + 14 * i, j = tc + 32 * c;
+                if (r < N && j < N) {
+                    const int sr = step_of[r], pj = rowpiv[j];
+                    if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
+                }
+            }
+    }
     if (t == 0 && info) info[blockIdx.x] = zeros;
 }
 
@@ -621,11 +687,11 @@ size_t gj_work_doubles(int N, int nblocks) {
 void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, double* tmp,
                 double* work, hipStream_t s) {
     if (N <= 64) {
-        k_gj_tile<4, 2><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
+        k_gj_tile<5, 2, 1><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 128) {
-        k_gj_tile<8, 4><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
+        k_gj_tile<10, 4, 2><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 192) {
-        k_gj_tile<12, 6><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
+        k_gj_tile<14, 6, 3><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else {
         const size_t NN = (size_t)N * N;
         GjWork w;

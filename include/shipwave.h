@@ -213,6 +213,12 @@ typedef struct {
 } sw_result;
 
 int32_t shipwave_server_create(const sw_server_opts* opts, sw_server** out);
+/* Device bytes a server with these options charges against hbm_budget_bytes when it
+ * admits this request with no cached preconditioner: the solve state plus the
+ * preconditioner (band factors and substitution operators).  Host-only; SW_EINVAL for
+ * an invalid request. */
+int32_t shipwave_server_request_bytes(const sw_server_opts* opts, const sw_request* req,
+                                      uint64_t* bytes);
 /* Queue one request; returns a ticket.  The server copies the request. */
 int32_t shipwave_server_submit(sw_server* s, const sw_request* req, uint64_t* ticket);
 /* SW_OK with *res filled (and zeta copied to zeta_host if non-NULL, N*M

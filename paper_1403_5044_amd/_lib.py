@@ -81,6 +81,8 @@ SIGNATURES = {
     "shipwave_profile_enable": (I32, [I32]),
     "shipwave_profile_read": (I32, [C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]),
     "shipwave_server_create": (I32, [C.POINTER(SwServerOpts), C.POINTER(P)]),
+    "shipwave_server_request_bytes": (I32, [C.POINTER(SwServerOpts), C.POINTER(SwRequest),
+                                            C.POINTER(C.c_uint64)]),
     "shipwave_server_submit": (I32, [P, C.POINTER(SwRequest), C.POINTER(C.c_uint64)]),
     "shipwave_server_poll": (I32, [P, C.c_uint64, C.POINTER(SwResult), P]),
     "shipwave_server_drain": (I32, [P]),

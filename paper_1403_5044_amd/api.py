@@ -252,14 +252,27 @@ class Server:
         o.precision = PRECISION[precision]
         h = C.c_void_p()
         L.check(self.lib.shipwave_server_create(C.byref(o), C.byref(h)))
+        self.opts = o
         self.handle = h
         self.meshes = {}
 
-    def submit(self, F, eps, N, M, x1, xN, yM) -> int:
+    @staticmethod
+    def _request(F, eps, N, M, x1, xN, yM):
         r = L.SwRequest()
         r.mesh.N, r.mesh.M = N, M
         r.domain.x1, r.domain.xN, r.domain.yM = x1, xN, yM
         r.F, r.eps = F, eps
+        return r
+
+    def request_bytes(self, F, eps, N, M, x1, xN, yM) -> int:
+        """Device bytes the server charges for this request (state + preconditioner)."""
+        b = C.c_uint64()
+        L.check(self.lib.shipwave_server_request_bytes(
+            C.byref(self.opts), C.byref(self._request(F, eps, N, M, x1, xN, yM)), C.byref(b)))
+        return b.value
+
+    def submit(self, F, eps, N, M, x1, xN, yM) -> int:
+        r = self._request(F, eps, N, M, x1, xN, yM)
         t = C.c_uint64()
         L.check(self.lib.shipwave_server_submit(self.handle, C.byref(r), C.byref(t)))
         self.meshes[t.value] = N * M

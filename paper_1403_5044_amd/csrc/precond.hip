@@ -515,13 +515,13 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 }
 
 // ---- N > 192: the block in global memory, one panel and one update launch per panel ----
-// Panel kernel: one workgroup per block, thread r holds row r of the panel (N <= 1024).
-// One block barrier per step: every wavefront posts its best candidate (key, row,
-// and the row already scaled by the candidate's reciprocal) in a double-buffered
-// LDS slot; after the barrier every thread takes the best of the 16 posts.
-// It writes the new panel columns pn[N][kPWG], the old pivot rows z[kPWG][N],
-// step_of[N] and rowpiv[N] (per block, in the workspace).
-constexpr int kGP = 1024;
+// Panel kernel: one 256-thread workgroup per block; thread t holds panel rows
+// t + 256 i (i < RW, N <= 256 RW).  One block barrier per step: every wavefront posts
+// its best candidate (key, row, and the row already scaled by the candidate's
+// reciprocal) in a double-buffered LDS slot; after the barrier every thread takes the
+// best of the 4 posts.  It writes the new panel columns pn[N][kPWG], the old pivot rows
+// z[kPWG][N], step_of[N] and rowpiv[N] (per block, in the workspace).
+constexpr int kGP = 256;
 constexpr int kPWG = 16;
 
 struct GjWork {
@@ -530,80 +530,110 @@ struct GjWork {
     int* piv;     // [nblocks][2][N]: step_of, rowpiv
 };
 
+template <int RW>
 __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restrict__ base,
                                                    size_t stride, GjWork w, int k0,
                                                    int* __restrict__ info) {
+    constexpr int NW = kGP / 64;
     const double* B = base + (size_t)blockIdx.x * stride;
     double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
     double* z = w.z + (size_t)blockIdx.x * kPWG * N;
     int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
     int* rowpiv = step_of + N;
-    __shared__ double rec[2][16][kPWG + 1];  // scaled candidate row, then its pivot value
-    __shared__ int ckey[2][16], crow[2][16], rp_s[kPWG];
-    const int r = threadIdx.x, lane = r & 63, wv = r >> 6;
+    __shared__ double rec[2][NW][kPWG + 1];  // scaled candidate row, then its pivot value
+    __shared__ int ckey[2][NW], crow[2][NW], rp_s[kPWG];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int kb = min(kPWG, N - k0);
-    const bool valid = r < N;
-    int st = (valid && k0 > 0) ? step_of[r] : -1;
-    double pv[kPWG];
+    int st[RW];
+    double pv[RW][kPWG];
 #pragma unroll
-    for (int u = 0; u < kPWG; ++u)
-        pv[u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
+    for (int i = 0; i < RW; ++i) {
+        const int r = t + kGP * i;
+        const bool valid = r < N;
+        st[i] = valid ? ((k0 > 0) ? step_of[r] : -1) : N;  // N marks padding
+#pragma unroll
+        for (int u = 0; u < kPWG; ++u)
+            pv[i][u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
+    }
     int zeros = 0;
 #pragma unroll
     for (int s = 0; s < kPWG; ++s) {
-        if (s >= kb) break;
+        if (s >= kb) continue;  // uniform; keeps the trip count constant for full unrolling
         const int buf = s & 1;
-        const bool cand = valid && st < 0;
-        const int key = cand ? pivot_key(pv[s]) : -1;
+        int key = -1, bi = -1;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int kk = pivot_key(pv[i][s]);
+            if (st[i] < 0 && kk > key) {
+                key = kk;
+                bi = i;
+            }
+        }
         const int wm = wave_max_i32(key);
-        const unsigned long long mask = __ballot(cand && key == wm);
+        const unsigned long long mask = __ballot(bi >= 0 && key == wm);
         const int wl = mask ? __builtin_ctzll(mask) : -1;
         if (lane == wl) {
-            const double d = rcp64(pv[s]);
 #pragma unroll
-            for (int u = 0; u < kPWG; ++u) rec[buf][wv][u] = (u == s) ? d : pv[u] * d;
-            rec[buf][wv][kPWG] = pv[s];
+            for (int i = 0; i < RW; ++i)
+                if (i == bi) {
+                    const double d = rcp64(pv[i][s]);
+#pragma unroll
+                    for (int u = 0; u < kPWG; ++u) rec[buf][wv][u] = (u == s) ? d : pv[i][u] * d;
+                    rec[buf][wv][kPWG] = pv[i][s];
+                }
         }
         if (lane == 0) {
             ckey[buf][wv] = mask ? wm : -1;
-            crow[buf][wv] = mask ? wv * 64 + wl : -1;
+            crow[buf][wv] = mask ? wv * 64 + wl + kGP * max(0, __builtin_amdgcn_readlane(bi, max(wl, 0))) : -1;
         }
         __syncthreads();
-        const int ck = (lane < 16) ? ckey[buf][lane] : -1;
-        const int gm = __builtin_amdgcn_readlane(row16_max_i32(ck), 0);
-        const unsigned long long m2 = __ballot(lane < 16 && ck >= 0 && ck == gm);
-        const int ww = m2 ? __builtin_ctzll(m2) : 0;
-        const int rp = max(0, min(N - 1, crow[buf][ww]));
+        int gw = 0, gk = ckey[buf][0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const int kq = ckey[buf][q];
+            if (kq > gk) {
+                gk = kq;
+                gw = q;
+            }
+        }
+        const int rp = max(0, min(N - 1, crow[buf][gw]));
         double pd[kPWG];
 #pragma unroll
-        for (int u = 0; u < kPWG; ++u) pd[u] = rec[buf][ww][u];
+        for (int u = 0; u < kPWG; ++u) pd[u] = rec[buf][gw][u];
         const double d = pd[s];
-        if (r == rp) {
 #pragma unroll
-            for (int u = 0; u < kPWG; ++u) pv[u] = pd[u];
-            st = k0 + s;
-        } else {
-            const double m = pv[s];
+        for (int i = 0; i < RW; ++i) {
+            if (t + kGP * i == rp) {
 #pragma unroll
-            for (int u = 0; u < kPWG; ++u) pv[u] = (u == s) ? -m * d : fma(-m, pd[u], pv[u]);
+                for (int u = 0; u < kPWG; ++u) pv[i][u] = pd[u];
+                st[i] = k0 + s;
+            } else {
+                const double m = pv[i][s];
+#pragma unroll
+                for (int u = 0; u < kPWG; ++u) pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
+            }
         }
-        if (r == 0) {
+        if (t == 0) {
             rp_s[s] = rp;
             rowpiv[k0 + s] = rp;
-            if (!(fabs(rec[buf][ww][kPWG]) > 0.0)) ++zeros;
+            if (!(fabs(rec[buf][gw][kPWG]) > 0.0)) ++zeros;
         }
     }
-    if (valid) {
 #pragma unroll
-        for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[u];
-        step_of[r] = st;
+    for (int i = 0; i < RW; ++i) {
+        const int r = t + kGP * i;
+        if (r < N) {
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[i][u];
+            step_of[r] = st[i];
+        }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kb * N; e += kGP) {
+    for (int e = t; e < kb * N; e += kGP) {
         const int tt = e / N, j = e - tt * N;
         z[(size_t)tt * N + j] = B[(size_t)rp_s[tt] * N + j];
     }
-    if (r == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
+    if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
 
 // Rank-kb update of every column outside the panel; the panel columns take pn.
@@ -700,7 +730,10 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
         w.piv = reinterpret_cast<int*>(work + (size_t)nblocks * 2 * kPWG * N);
         const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
         for (int k0 = 0; k0 < N; k0 += kPWG) {
-            k_gjp_panel<<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+            if (N <= 2 * kGP)
+                k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+            else
+                k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
             k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);
         }
         const unsigned ge = (unsigned)std::min<size_t>((NN + 255) / 256, 2048);

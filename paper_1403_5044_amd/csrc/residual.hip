@@ -262,12 +262,13 @@ __global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict_
 }
 
 // ---- a5: the all-pairs sum ----------------------------------------------------------
-// 1/sqrt(x) in FP64: hardware estimate plus one Newton-Raphson step,
-// y1 = y0 + y0 (1 - x y0^2) / 2, relative error 1.5 e0^2 for an estimate error e0.
-__device__ __forceinline__ double rsq64(double x) {
+// 2/sqrt(x) in FP64: hardware estimate y0 plus one Newton-Raphson step written as
+// y0 (3 - x y0^2), which is twice the refined 1/sqrt(x) (relative error 1.5 e0^2 for
+// an estimate error e0) in three operations; the factors of 2 are taken out of the
+// row sums once per collocation point.
+__device__ __forceinline__ double rsq2_64(double x) {
     const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
+    return y * fma(-x * y, y, 3.0);
 }
 
 constexpr int kPairThreads = 256;
@@ -335,12 +336,17 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
                 const double dx2 = dx * dx;
                 const double dz = sz - zs[c];
                 const double h = fma(dz, dz, dx2);
-                const double i1 = rsq64(h + dy2[c]);
-                const double i2 = rsq64(h + dyp2[c]);
+                // doubled reciprocal distances: i = 2/r, and the sum j1s + j2s of the
+                // doubled 2/sqrt(q), whose last Newton products share one fma
+                const double i1 = rsq2_64(h + dy2[c]);
+                const double i2 = rsq2_64(h + dyp2[c]);
                 const double q1 = fma(dx, fma(A[c], dx, Bdy[c]), Cdy2[c]);
                 const double q2 = fma(dx, fma(A[c], dx, mBdyp[c]), Cdyp2[c]);
-                const double j1s = rsq64(q1);
-                const double j2s = rsq64(q2);
+                const double y1 = __builtin_amdgcn_rsq(q1);
+                const double y2 = __builtin_amdgcn_rsq(q2);
+                const double f1 = fma(-q1 * y1, y1, 3.0);
+                const double f2 = fma(-q2 * y2, y2, 3.0);
+                const double js = fma(y1, f1, y2 * f2);
                 const double n0 = fma(-dx, szx, dz);
                 const double n1 = fma(-dy[c], szy, n0);
                 const double n2 = fma(-dyp[c], szy, n0);
@@ -348,14 +354,15 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
                 const double wd = fma(-sw, ps[c], swp);
                 acc1[c] = fma(wd, K1, acc1[c]);
                 acc2[c] = fma(swzx, i1 + i2, acc2[c]);
-                acc3[c] = fma(sw, j1s + j2s, acc3[c]);
+                acc3[c] = fma(sw, js, acc3[c]);
             }
         }
     }
 #pragma unroll
     for (int c = 0; c < CP; ++c)
         if (idx[c] < g.ncol)
-            partial[(size_t)chunk * g.ncol + idx[c]] = acc1[c] + acc2[c] - zxs[c] * acc3[c];
+            partial[(size_t)chunk * g.ncol + idx[c]] =
+                fma(0.125, acc1[c], 0.5 * fma(-zxs[c], acc3[c], acc2[c]));
 }
 
 template <int CP>

@@ -144,19 +144,33 @@ void sw_server::start_task(Active& a, int precision) {
     a.task.reset(new SolveTask(a.g, a.prm, a.P, a.u, tmem, a.pin));
 }
 
+namespace {
+Geo request_geo(const sw_request& req) {
+    sw_problem p{};
+    p.mesh = req.mesh;
+    p.domain = req.domain;
+    p.params.F = req.F;
+    p.params.eps = req.eps;
+    p.params.nu = 0.05;
+    p.params.precision = SW_PREC_FP64;
+    return make_geo(p);
+}
+
+// device bytes of one admitted request: its solve state and, unless cached, its
+// preconditioner
+size_t task_bytes_of(const Geo& g) {
+    const int m = SolveParams{}.m;
+    return carve_size({2 * (size_t)g.NM * 8, (size_t)g.NM * 8}) + SolveTask::device_bytes(g, m) +
+           256;
+}
+}  // namespace
+
 bool sw_server::admit_one(std::unique_lock<std::mutex>& lk) {
     if (queue.empty() || (int)active.size() >= opts.max_slots) return false;
     Pending pd = queue.front();
-    sw_problem p{};
-    p.mesh = pd.req.mesh;
-    p.domain = pd.req.domain;
-    p.params.F = pd.req.F;
-    p.params.eps = pd.req.eps;
-    p.params.nu = 0.05;
-    p.params.precision = SW_PREC_FP64;
     Geo g;
     try {
-        g = make_geo(p);
+        g = request_geo(pd.req);
     } catch (const Error& e) {
         queue.pop_front();
         Finished f{};
@@ -168,9 +182,7 @@ bool sw_server::admit_one(std::unique_lock<std::mutex>& lk) {
         cv_done.notify_all();
         return true;
     }
-    const int m = SolveParams{}.m;
-    const size_t task_bytes = carve_size({2 * (size_t)g.NM * 8, (size_t)g.NM * 8}) +
-                              SolveTask::device_bytes(g, m) + 256;
+    const size_t task_bytes = task_bytes_of(g);
     const bool cached = pcache.count(pkey(g)) > 0;
     const size_t p_bytes = cached ? 0 : precond_bytes_estimate(g, opts.q_blocks);
     const double budget = opts.hbm_budget_bytes;
@@ -364,6 +376,17 @@ int32_t shipwave_server_create(const sw_server_opts* opts, sw_server** out) {
         }
         s->worker = std::thread([s] { s->run(); });
         *out = s;
+        return SW_OK;
+    });
+}
+
+int32_t shipwave_server_request_bytes(const sw_server_opts* opts, const sw_request* req,
+                                      uint64_t* bytes) {
+    return guard([&]() -> int32_t {
+        SW_REQUIRE(opts && req && bytes, "null pointer");
+        const Geo g = request_geo(*req);
+        const int q = opts->q_blocks < 0 ? 4 : opts->q_blocks;
+        *bytes = (uint64_t)(task_bytes_of(g) + precond_bytes_estimate(g, q));
         return SW_OK;
     });
 }

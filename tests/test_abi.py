@@ -42,3 +42,26 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.SwProblem) == 8 + 24 + 40
     assert ctypes.sizeof(_lib.SwParams) == 40
     assert ctypes.sizeof(_lib.SwSolveOpts) == 8 + 8 * 4 + 8 + 8 + 8
+
+
+def test_request_footprint_query_is_host_only_and_monotone():
+    """shipwave_server_request_bytes runs on the host: the charge grows with the mesh
+    and with the preconditioner bandwidth, and an invalid mesh is rejected."""
+    lib = _lib.load()
+
+    def charge(N, M, q):
+        o = _lib.SwServerOpts()
+        o.hbm_budget_bytes, o.max_slots, o.q_blocks = 8e9, 4, q
+        r = _lib.SwRequest()
+        r.mesh.N, r.mesh.M = N, M
+        r.domain.x1, r.domain.xN, r.domain.yM = -16.0, 8.0, 12.0
+        r.F, r.eps = 0.7, 0.1
+        b = ctypes.c_uint64()
+        rc = lib.shipwave_server_request_bytes(ctypes.byref(o), ctypes.byref(r), ctypes.byref(b))
+        return rc, b.value
+
+    rc, small = charge(61, 21, 4)
+    assert rc == 0 and small > 61 * 21 * 16
+    assert charge(181, 61, 4)[1] > small
+    assert charge(181, 61, 8)[1] > charge(181, 61, 4)[1]
+    assert charge(3, 21, 4)[0] == -1

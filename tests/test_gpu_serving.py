@@ -90,7 +90,9 @@ def test_server_admission_by_memory_budget():
     res = _serve(REQS[:2], precision="fp64", hbm_budget_bytes=1e5)
     assert all(r.status == -2 for r in res)
     # budget for one 61x21 request at a time: all complete, one after another
-    one = 12e6
+    probe = api.Server(precision="fp64")
+    one = 1.5 * max(probe.request_bytes(*REQS[1]), probe.request_bytes(*REQS[2]))
+    probe.close()
     res = _serve([REQS[1], REQS[2]], precision="fp64", hbm_budget_bytes=one, max_slots=8)
     assert all(r.status == 0 for r in res)
     assert res[1].t_admit_s >= res[0].t_done_s - 1e-6

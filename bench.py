@@ -4,14 +4,17 @@
 One step = one complete FP64 Jacobian-free Newton-Krylov solve of the 181 x 61
 workload (x in [-16, 8], y in [0, 12], eps = 0.1, F = 0.7) from the flat
 surface to ||E||_inf <= 1e-10, including the set-up of the banded
-linear-Jacobian preconditioner (block half-bandwidth q, default 1).  Inputs
+linear-Jacobian preconditioner (block half-bandwidth q, default 4).  Inputs
 are synthetic (the flat state), device-resident before timing starts.
 
 Printed on one JSON line:
   value          solves/s over the timed steps (whole job, one GPU)
   roofline       the all-pairs residual kernel, timed live with HIP events on
                  its launch stream: 48 algorithmic flops per (collocation,
-                 grid) pair against the FP64 vector peak of the MI355X
+                 grid) pair against the FP64 vector peak of the MI355X; HBM
+                 traffic and the instruction-counted FP64 rate come from the
+                 committed rocprofv3 counter summaries in profiles/ (null once
+                 the kernel source differs from the one they were taken on)
   cpu_baseline   the FP64 CPU oracle on a bounded sample of the same workload
   extra          residual throughput on the 16-state batch (FP64, FP32-Kahan),
                  solve with a prebuilt preconditioner, mixed-precision solve,
@@ -46,23 +49,43 @@ def parse():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--residuals", action="store_true",
+                    help="residual throughput on configs 1-4, FP64 and FP32-Kahan (own line)")
+    ap.add_argument("--workloads", action="store_true",
+                    help="config-3 solves (F x eps grid, FP64 and mixed) and the config-4 "
+                         "eps continuation (own line)")
     return ap.parse_args()
 
 
-def measured_traffic():
-    """HBM bytes per all-pairs launch from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+def _counter_record(name):
+    """A committed counter summary for the all-pairs kernel, or None when the
+    kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_pairs_f64_181x61_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_1403_5044_amd", "csrc", "residual.hip")
     try:
         rec = json.load(open(path))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    if rec.get("source_sha256") != digest:
+    return rec if rec.get("source_sha256") == digest else None
+
+
+def measured_traffic():
+    """HBM bytes per all-pairs launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    rec = _counter_record("k_pairs_f64_181x61_hbm_counters.json")
+    return rec["traffic_bytes_per_launch"] if rec else None
+
+
+def counted_rate(avg_ms):
+    """FP64 rate counted by instruction type (64 lanes x (2 FMA + MUL + ADD + TRANS)
+    per wave instruction, from SQ_INSTS_VALU_*_F64) over the live launch time."""
+    rec = _counter_record("k_pairs_f64_181x61_fp64_inst_counters.json")
+    if not rec or not avg_ms:
         return None
-    return rec["traffic_bytes_per_launch"]
+    tf = rec["counted_flops_per_dispatch"] / (avg_ms * 1e-3) / 1e12
+    return {"tflops": tf, "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+            "flops_per_pair": rec["counted_flops_per_pair"]}
 
 
 def cpu_baseline(cfg, evals_per_solve):
@@ -98,6 +121,10 @@ def main():
         return calibrate_copy()
     if args.serving:
         return serving(args)
+    if args.residuals:
+        return residuals()
+    if args.workloads:
+        return workloads()
     import torch
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
@@ -142,7 +169,7 @@ def main():
                 "traffic": measured_traffic(),
                 "kernel": "k_pairs_f64 (all-pairs boundary-integral sum)",
                 "launches": launches, "avg_launch_ms": avg_ms,
-                "flop_per_launch": flops_per_launch}
+                "flop_per_launch": flops_per_launch, "counted": counted_rate(avg_ms)}
     extra = {"newton_iters": infos[-1].newton_iters, "gmres_iters": infos[-1].gmres_iters,
              "residual_evals": infos[-1].residual_evals,
              "precond_build_s": infos[-1].time_precond_s,
@@ -283,6 +310,113 @@ def serving(args):
             "p99_latency_s": out["poisson_fp32"]["p99_latency_s"],
             "arrival_rate_per_s": rate, "runs": out}
     print(json.dumps(line), flush=True)
+
+
+def _line(value, unit, workload, extra, dtype="f64", higher=True):
+    return {"metric": "JFNK solves/s & pair-interactions/s (frac FP64 peak); p50/p99 solve latency",
+            "value": value, "unit": unit, "n_gpus": 1, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": {"workload": workload}, **extra}
+
+
+def residuals():
+    """Whole-residual throughput (prelude, pair sum and finish) on configs 1-4 from a
+    smooth synthetic state, each precision timed over repeated calls with HIP events."""
+    import torch
+    from paper_1403_5044_amd import api, inputs
+    from paper_1403_5044_amd import _lib
+    _lib.load()
+    rows = {}
+    for name, cfg, reps in (("config1", inputs.CONFIG1, 50), ("config2", inputs.CONFIG2, 50),
+                            ("config3", inputs.CONFIG3, 10), ("config4", inputs.CONFIG4, 3)):
+        for prec in ("fp64", "fp32"):
+            p = api.Problem(**cfg, precision=prec)
+            u = torch.tensor(inputs.smooth_state(p.N, p.M, 0.02, 1), device="cuda")
+            E = api.residual(p, u)
+            torch.cuda.synchronize()
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(reps):
+                api.residual(p, u, out=E)
+            e.record()
+            torch.cuda.synchronize()
+            ms = s.elapsed_time(e) / reps
+            rows[f"{name}_{prec}"] = {
+                "mesh": f"{p.N}x{p.M}", "ms_per_residual": ms, "pairs_per_s": p.pairs / ms * 1e3,
+                "algorithmic_tflops": FLOP_PER_PAIR * p.pairs / ms * 1e-9,
+                "frac_of_peak": FLOP_PER_PAIR * p.pairs / ms * 1e-9 /
+                (FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else 2 * FP64_VECTOR_PEAK_TFLOPS)}
+    print(json.dumps(_line(rows["config4_fp64"]["pairs_per_s"], "pairs/s",
+                           "whole residual E(u) on configs 1-4 (smooth state), FP64 and FP32-Kahan",
+                           {"rows": rows})), flush=True)
+
+
+def workloads():
+    """Config 3: 361x121 on the paper's domain, F in {0.5, 0.7, 1.0} x eps in {0.1, 0.3},
+    each solved in FP64 and in mixed precision with one preconditioner per F (q = 8).
+    Config 4: 721x241, F = 0.7, eps continued 0.1 -> 0.5 in mixed precision (q = 8), with
+    FP64 solves at the first and last eps for comparison."""
+    import torch
+    from paper_1403_5044_amd import api, inputs
+    from paper_1403_5044_amd import _lib
+    _lib.load()
+    kw = dict(tol=1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
+
+    def timed(F, eps, cfg, prec, P, u0=None):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, z, info = api.solve(F, eps, cfg["N"], cfg["M"], cfg["x1"], cfg["xN"], cfg["yM"],
+                               precision=prec, precond=P, u0=u0, **kw)
+        torch.cuda.synchronize()
+        return u, z, {"status": info.status, "newton": info.newton_iters,
+                      "gmres": info.gmres_iters, "evals": info.residual_evals,
+                      "final_norm": info.final_norm, "s": time.perf_counter() - t0,
+                      "zeta_max": z.max().item()}
+
+    def build(cfg, q):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = api.Preconditioner(api.Problem(**cfg), q)
+        torch.cuda.synchronize()
+        return P, time.perf_counter() - t0
+
+    out = {"config3": [], "config4": []}
+    c3 = inputs.CONFIG3
+    for F in inputs.CONFIG3_F:
+        P, tb = build(dict(c3, F=F), 8)
+        for eps in inputs.CONFIG3_EPS:
+            _, z64, r64 = timed(F, eps, c3, "fp64", P)
+            _, z32, r32 = timed(F, eps, c3, "fp32", P)
+            out["config3"].append({"F": F, "eps": eps, "build_s": tb, "fp64": r64, "mixed": r32,
+                                   "zeta_mixed_vs_fp64": (z64 - z32).abs().max().item()})
+            print(f"config3 F={F} eps={eps}: fp64 {r64['s']:.2f}s mixed {r32['s']:.2f}s",
+                  file=sys.stderr, flush=True)
+        P.close()
+    c4 = inputs.CONFIG4
+    P, tb = build(c4, 8)
+    out["config4_build_s"] = tb
+    u = None
+    for eps in inputs.CONFIG4_EPS:
+        um, zm, rm = timed(c4["F"], eps, c4, "fp32", P, u)
+        rec = {"eps": eps, "mixed": rm}
+        if eps in (inputs.CONFIG4_EPS[0], inputs.CONFIG4_EPS[-1]):
+            _, z64, r64 = timed(c4["F"], eps, c4, "fp64", P, u)
+            rec["fp64"] = r64
+            rec["zeta_mixed_vs_fp64"] = (z64 - zm).abs().max().item()
+        out["config4"].append(rec)
+        print(f"config4 eps={eps}: mixed {rm['s']:.2f}s status {rm['status']}", file=sys.stderr,
+              flush=True)
+        if rm["status"] != 0:
+            break
+        u = um
+    P.close()
+    n = len(out["config4"])
+    total = sum(r["mixed"]["s"] for r in out["config4"])
+    print(json.dumps(_line(n / total, "solves/s",
+                           "config-4 eps continuation 0.1..0.5 (721x241, mixed, q=8); "
+                           "config-3 F x eps grid in FP64 and mixed (361x121, q=8)",
+                           {"runs": out}, dtype="f32+f64")), flush=True)
 
 
 if __name__ == "__main__":

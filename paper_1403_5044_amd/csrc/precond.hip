@@ -754,70 +754,76 @@ struct GemmBatch {
     GemmJob j[kMaxGemmJobs];
 };
 
-// FP64 matrix cores (v_mfma_f64_16x16x4f64): a 64 x 64 tile of C per workgroup,
-// 32 x 32 (2 x 2 MFMA tiles) per wavefront, K staged through LDS 16 at a time with
-// the next slice prefetched into registers.  Operand layout of the instruction:
-// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane
-// l is C[l / 16 + 4 r][l % 16].
+// FP64 matrix cores (v_mfma_f64_16x16x4f64): four wavefronts per workgroup in a 2 x 2
+// arrangement, each computing WM x WN MFMA tiles of 16 x 16 (a (32 WM) x (32 WN) tile of C
+// per workgroup; 64 x 64 for large blocks, 32 x 32 for N <= 256 so that small products
+// still fill the chip), K staged through LDS 16 at a time with the next slice prefetched
+// into registers.  Operand layout of the instruction: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result register r of lane l is C[l / 16 + 4 r][l % 16].
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kGK = 16;
 
+template <int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch batch) {
+    constexpr int TM = 32 * WM, TN = 32 * WN;
+    constexpr int EA = TM * kGK / 256, EB = TN * kGK / 256;  // slice elements per thread
     const GemmJob job = batch.j[blockIdx.z];
     const double* __restrict__ A = job.A;
     const double* __restrict__ B = job.B;
-    __shared__ double As[64][kGK + 1];
-    __shared__ double Bs[kGK][64 + 2];
+    __shared__ double As[TM][kGK + 1];
+    __shared__ double Bs[kGK][TN + 2];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    dbl4 acc[2][2];
+    const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int wr = (w >> 1) * 16 * WM, wc = (w & 1) * 16 * WN;
+    dbl4 acc[WM][WN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    const int ar = t >> 2, ak = (t & 3) * 4;   // A slice 64 x 16: row ar, k ak..ak+3
-    const int bk = t >> 4, bc = (t & 15) * 4;  // B slice 16 x 64: k bk, cols bc..bc+3
-    double ra[4], rb[4];
+        for (int b = 0; b < WN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int ar = t / (kGK / EA), ak = (t % (kGK / EA)) * EA;  // A slice TM x 16
+    const int bk = t / (TN / EB), bc = (t % (TN / EB)) * EB;    // B slice 16 x TN
+    double ra[EA], rb[EB];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < EA; ++e) {
             const int gr = row0 + ar, gk = k0 + ak + e;
             ra[e] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : 0.0;
-            const int gk2 = k0 + bk, gc = col0 + bc + e;
-            rb[e] = (gk2 < n && gc < n) ? B[(size_t)gk2 * n + gc] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int gk = k0 + bk, gc = col0 + bc + e;
+            rb[e] = (gk < n && gc < n) ? B[(size_t)gk * n + gc] : 0.0;
         }
     };
     load(0);
     for (int k0 = 0; k0 < n; k0 += kGK) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            As[ar][ak + e] = ra[e];
-            Bs[bk][bc + e] = rb[e];
-        }
+        for (int e = 0; e < EA; ++e) As[ar][ak + e] = ra[e];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) Bs[bk][bc + e] = rb[e];
         __syncthreads();
         if (k0 + kGK < n) load(k0 + kGK);
 #pragma unroll
         for (int k4 = 0; k4 < kGK; k4 += 4) {
-            double fa[2], fb[2];
+            double fa[WM], fb[WN];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = As[wr + a * 16 + (lane & 15)][k4 + (lane >> 4)];
+            for (int a = 0; a < WM; ++a) fa[a] = As[wr + a * 16 + (lane & 15)][k4 + (lane >> 4)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = Bs[k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+            for (int b = 0; b < WN; ++b) fb[b] = Bs[k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < WM; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < WN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
     }
     const double* Cin = job.Cin;
     double* C = job.C;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int gr = row0 + wr + a * 16 + (lane >> 4) + 4 * r;
@@ -828,6 +834,7 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
                 }
             }
 }
+
 
 
 // ---- apply ----------------------------------------------------------------------------
@@ -970,41 +977,38 @@ __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const doub
     if (lane == 0) x[wid] = p;
 }
 
-// One wavefront per output row of a super-row step (SuperStep); four terms'
-// loads are issued together.
+// One workgroup per output row of a super-row step (SuperStep): its four wavefronts
+// take every fourth term, so that each has few dependent load rounds, and the four
+// partial dot products are added in a fixed order.
 __global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st,
                                                     double* __restrict__ out) {
-    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (wid >= st.nrow * N) return;
-    const int i = wid / N, r = wid - i * N;
+    const int row = blockIdx.x;
+    const int i = row / N, r = row - i * N;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int t0 = st.first[i], t1 = st.first[i + 1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
+    double s0 = 0.0, s1 = 0.0;
+    int t = t0 + w;
+    for (; t + 4 < t1; t += 8) {
         const double* b0 = st.blk[t] + (size_t)r * N;
-        const double* b1 = st.blk[t + 1] + (size_t)r * N;
-        const double* b2 = st.blk[t + 2] + (size_t)r * N;
-        const double* b3 = st.blk[t + 3] + (size_t)r * N;
+        const double* b1 = st.blk[t + 4] + (size_t)r * N;
         const double* v0 = st.vec[t];
-        const double* v1 = st.vec[t + 1];
-        const double* v2 = st.vec[t + 2];
-        const double* v3 = st.vec[t + 3];
+        const double* v1 = st.vec[t + 4];
         for (int n = lane; n < N; n += 64) {
             s0 = fma(b0[n], v0[n], s0);
             s1 = fma(b1[n], v1[n], s1);
-            s2 = fma(b2[n], v2[n], s2);
-            s3 = fma(b3[n], v3[n], s3);
         }
     }
-    for (; t < t1; ++t) {
+    if (t < t1) {
         const double* b0 = st.blk[t] + (size_t)r * N;
         const double* v0 = st.vec[t];
         for (int n = lane; n < N; n += 64) s0 = fma(b0[n], v0[n], s0);
     }
-    double sum = (s0 + s1) + (s2 + s3);
+    double sum = s0 + s1;
     for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
-    if (lane == 0) out[wid] = sum;
+    __shared__ double part[4];
+    if (lane == 0) part[w] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) out[row] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // dst = 0, I, src or -src for a batch of N x N blocks; grid (chunks, jobs)
@@ -1044,8 +1048,13 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
         GemmBatch batch{};
         const int cnt = (int)std::min<size_t>(kMaxGemmJobs, jobs.size() - b);
         for (int i = 0; i < cnt; ++i) batch.j[i] = jobs[b + i];
-        dim3 grid((n + 63) / 64, (n + 63) / 64, cnt);
-        k_gemm<<<grid, 256, 0, s>>>(n, alpha, batch);
+        if (n <= 256) {
+            dim3 grid((n + 31) / 32, (n + 31) / 32, cnt);
+            k_gemm<1, 1><<<grid, 256, 0, s>>>(n, alpha, batch);
+        } else {
+            dim3 grid((n + 63) / 64, (n + 63) / 64, cnt);
+            k_gemm<2, 2><<<grid, 256, 0, s>>>(n, alpha, batch);
+        }
     }
 }
 
@@ -1080,7 +1089,10 @@ int k3_chunks(const Geo& g) {
 // on their right-hand sides (GEMMs), keeping only the nonzero blocks, and each
 // application then takes 2 ceil(M/b) launches instead of 2M.
 namespace {
-constexpr double kSuperTarget = 1000.0;  // b N: super-row height in grid rows
+#ifndef SW_SUPER_TARGET
+#define SW_SUPER_TARGET 1000.0
+#endif
+constexpr double kSuperTarget = SW_SUPER_TARGET;  // b N: super-row height in grid rows
 
 struct SuperRow {
     int l0 = 0, nb = 0, nprev = 0;   // first block row, block rows, coupled outside blocks
@@ -1441,13 +1453,13 @@ void enqueue_substitution(const sw_precond* P, hipStream_t s) {
         // y in tmp, x in s2 (the step arguments point there)
         for (size_t k = 0; k < P->fsteps.size(); ++k) {
             const SuperStep& st = P->fsteps[k];
-            k_super_step<<<(unsigned)((st.nrow * N * 64 + 255) / 256), 256, 0, s>>>(
-                N, st, tmp + (size_t)P->sl0[k] * N);
+            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st,
+                                                                 tmp + (size_t)P->sl0[k] * N);
         }
         for (size_t k = P->bsteps.size(); k-- > 0;) {
             const SuperStep& st = P->bsteps[k];
-            k_super_step<<<(unsigned)((st.nrow * N * 64 + 255) / 256), 256, 0, s>>>(
-                N, st, s2 + (size_t)P->sl0[k] * N);
+            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st,
+                                                                 s2 + (size_t)P->sl0[k] * N);
         }
         return;
     }

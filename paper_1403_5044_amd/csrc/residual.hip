@@ -272,6 +272,12 @@ __device__ __forceinline__ double rsq2_64(double x) {
 }
 
 constexpr int kPairThreads = 256;
+#ifndef SW_UNROLL64
+#define SW_UNROLL64 2  // source points per FP64 inner-loop iteration
+#endif
+#ifndef SW_WPE64
+#define SW_WPE64 1  // minimum waves per SIMD asked of the FP64 pair kernels' register use
+#endif
 
 template <int CP>
 __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __restrict__ src,
@@ -324,7 +330,7 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
             Cdy2[c] = C[c] * dy2[c];
             Cdyp2[c] = C[c] * dyp2[c];
         }
-#pragma unroll 2
+#pragma unroll SW_UNROLL64
         for (int i = i0; i < i1; ++i) {
             const double4 r0 = reinterpret_cast<const double4*>(lds + i * 8)[0];
             const double4 r1 = reinterpret_cast<const double4*>(lds + i * 8)[1];
@@ -366,7 +372,7 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
 }
 
 template <int CP>
-__global__ __launch_bounds__(kPairThreads) void k_pairs_f64(Geo g, const double* __restrict__ src,
+__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(SW_WPE64))) void k_pairs_f64(Geo g, const double* __restrict__ src,
                                                             const double* __restrict__ col,
                                                             double* __restrict__ partial,
                                                             int ntiles, int G) {
@@ -507,7 +513,7 @@ struct PairBatch {
 };
 
 template <int CP>
-__global__ __launch_bounds__(kPairThreads) void k_pairs_f64_batched(PairBatch b) {
+__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(SW_WPE64))) void k_pairs_f64_batched(PairBatch b) {
     extern __shared__ double lds[];
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     int q = 0;

@@ -190,19 +190,22 @@ __global__ __launch_bounds__(128) void k_spline_dense(Geo g, const double* __res
     if (k >= g.N) return;
     const double* F = (f == 0 ? psi : zeta) + k;
     const double* q = Q + (size_t)j * g.M;
-    double s0 = 0.0, s1 = 0.0;
+    double s[8] = {};  // eight independent chains: eight loads in flight
     int m = 0;
-    for (; m + 1 < g.M; m += 2) {
-        s0 = fma(q[m], F[(size_t)m * g.N], s0);
-        s1 = fma(q[m + 1], F[(size_t)(m + 1) * g.N], s1);
-    }
-    if (m < g.M) s0 = fma(q[m], F[(size_t)m * g.N], s0);
-    (f == 0 ? psiy : zetay)[(size_t)j * g.N + k] = (s0 + s1) / g.dy;
+    for (; m + 7 < g.M; m += 8)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] = fma(q[m + e], F[(size_t)(m + e) * g.N], s[e]);
+    for (; m < g.M; ++m) s[0] = fma(q[m], F[(size_t)m * g.N], s[0]);
+    const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    (f == 0 ? psiy : zetay)[(size_t)j * g.N + k] = t / g.dy;
 }
 
 // Source record (64 B): x, zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
 // FP32 source record (32 B): i (exact), zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
 // Collocation record (64 B): x*, y*, zeta*, psi*, zeta_x*, zeta_y*, E2 local part, -
+// Eight lanes per grid point: lane 0 writes the source record and, for a collocation
+// point, E1 and the collocation record; the eight log integrals of the closed-form I
+// are spread over the eight lanes and added by shuffles.
 __global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict__ u,
                                                 const double* __restrict__ psi,
                                                 const double* __restrict__ zeta,
@@ -212,47 +215,56 @@ __global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict_
                                                 float* __restrict__ src32,
                                                 double* __restrict__ col,
                                                 double* __restrict__ E) {
-    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= g.NM) return;
-    const int l = gi / g.N;
-    const int k = gi - l * g.N;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gi = tid >> 3, sub = tid & 7;
+    const bool live = gi < g.NM;  // no early exit: the eight lanes shuffle below
+    const int gs = live ? gi : 0;
+    const int l = gs / g.N;
+    const int k = gs - l * g.N;
     const double* phx = u;
     const double* zx = u + g.NM;
     const double w = g.dx * g.dy * weight1d(k, g.N, g.weights) * weight1d(l, g.M, g.weights);
-    const double ps = psi[gi], ze = zeta[gi], zxv = zx[gi], zyv = zetay[gi];
-    {
-        double* r = src64 + (size_t)gi * 8;
+    const double ps = psi[gs], ze = zeta[gs], zxv = zx[gs], zyv = zetay[gs];
+    if (live && sub == 0) {
+        double* r = src64 + (size_t)gs * 8;
         const double x = g.x1 + k * g.dx;
         reinterpret_cast<double4*>(r)[0] = make_double4(x, ze, zxv, zyv);
         reinterpret_cast<double4*>(r)[1] = make_double4(w * ps, w, w * zxv, 0.0);
         if (g.precision == SW_PREC_FP32) {
-            float* s = src32 + (size_t)gi * 8;
-            reinterpret_cast<float4*>(s)[0] =
+            float* sp = src32 + (size_t)gs * 8;
+            reinterpret_cast<float4*>(sp)[0] =
                 make_float4((float)k, (float)ze, (float)zxv, (float)zyv);
-            reinterpret_cast<float4*>(s)[1] =
+            reinterpret_cast<float4*>(sp)[1] =
                 make_float4((float)(w * ps), (float)w, (float)(w * zxv), 0.0f);
         }
     }
-    if (k >= g.N - 1) return;
-    const int c = l * g.Nc + k;
-    const int g1 = gi + 1;
-    const double pxs = 0.5 * ((phx[gi] - 1.0) + (phx[g1] - 1.0));
-    const double pss = 0.5 * (ps + psi[g1]);
-    const double pys = 0.5 * (psiy[gi] + psiy[g1]);
+    const bool colpt = live && k < g.N - 1;
+    const int g1 = colpt ? gs + 1 : gs;
     const double zs = 0.5 * (ze + zeta[g1]);
     const double zxs = 0.5 * (zxv + zx[g1]);
     const double zys = 0.5 * (zyv + zetay[g1]);
+    const double den = 1.0 + zxs * zxs + zys * zys;
+    // singular-part quadratic form and its exact integral
+    const double A = 1.0 + zxs * zxs, B = 2.0 * zxs * zys, C = 1.0 + zys * zys;
+    const double xs = g.x1 + (k + 0.5) * g.dx;
+    const double ys = l * g.dy;
+    double part = colpt ? closed_form_I_part(sub >> 1, sub & 1, A, B, C, 4.0 * den, xs - g.x1,
+                                             g.xN - xs, ys, g.yM)
+                        : 0.0;
+    part += __shfl_xor(part, 1, 8);
+    part += __shfl_xor(part, 2, 8);
+    part += __shfl_xor(part, 4, 8);
+    if (!colpt || sub != 0) return;
+    const double I = part;
+    const int c = l * g.Nc + k;
+    const double pxs = 0.5 * ((phx[gs] - 1.0) + (phx[g1] - 1.0));
+    const double pss = 0.5 * (ps + psi[g1]);
+    const double pys = 0.5 * (psiy[gs] + psiy[g1]);
     // E1: Bernoulli condition with phi_x* = 1 + psi_x*, phi_y* = psi_y*
     const double fx = 1.0 + pxs, fy = pys;
     const double num = (1.0 + zxs * zxs) * fy * fy + (1.0 + zys * zys) * fx * fx -
                        2.0 * zxs * zys * fx * fy;
-    const double den = 1.0 + zxs * zxs + zys * zys;
     E[(size_t)l * g.N + k + 1] = 0.5 * num / den + zs / (g.F * g.F) - 0.5;
-    // Singular-part quadratic form and its exact integral
-    const double A = 1.0 + zxs * zxs, B = 2.0 * zxs * zys, C = 1.0 + zys * zys;
-    const double xs = g.x1 + (k + 0.5) * g.dx;
-    const double ys = l * g.dy;
-    const double I = closed_form_I(A, B, C, 4.0 * den, xs - g.x1, g.xN - xs, ys, g.yM);
     const double zp1 = zs + 1.0;
     const double srcterm = g.eps / sqrt(xs * xs + ys * ys + zp1 * zp1);
     const double base = kTwoPi * pss + srcterm - zxs * I;
@@ -274,6 +286,9 @@ __device__ __forceinline__ double rsq2_64(double x) {
 constexpr int kPairThreads = 256;
 #ifndef SW_UNROLL64
 #define SW_UNROLL64 2  // source points per FP64 inner-loop iteration
+#endif
+#ifndef SW_PAIR_TARGET
+#define SW_PAIR_TARGET 2048  // blocks per pair launch
 #endif
 #ifndef SW_WPE64
 #define SW_WPE64 1  // minimum waves per SIMD asked of the FP64 pair kernels' register use
@@ -542,16 +557,13 @@ __global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict_
                                                 double* __restrict__ E) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncol) return;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double t[8] = {};  // eight independent chains: eight loads in flight
     int q = 0;
-    for (; q + 3 < G; q += 4) {
-        s0 += partial[(size_t)q * g.ncol + c];
-        s1 += partial[(size_t)(q + 1) * g.ncol + c];
-        s2 += partial[(size_t)(q + 2) * g.ncol + c];
-        s3 += partial[(size_t)(q + 3) * g.ncol + c];
-    }
-    for (; q < G; ++q) s0 += partial[(size_t)q * g.ncol + c];
-    const double s = (s0 + s1) + (s2 + s3);
+    for (; q + 7 < G; q += 8)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] += partial[(size_t)(q + e) * g.ncol + c];
+    for (; q < G; ++q) t[0] += partial[(size_t)q * g.ncol + c];
+    const double s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
     const int l = c / g.Nc;
     const int k = c - l * g.Nc;
     E[(size_t)g.NM + (size_t)l * g.N + k + 1] = col[(size_t)c * 8 + 6] - s;
@@ -610,9 +622,11 @@ const double* spline_operator(int M, int bc, hipStream_t s) {
 int choose_chunks(const Geo& g) {
     const int cp = (g.precision == SW_PREC_FP32) ? kCP32 : kCP64;
     const int ntiles = (g.ncol + kPairThreads * cp - 1) / (kPairThreads * cp);
-    // About 2048 equal blocks: two full rounds at four 256-thread blocks per CU.
-    // A chunk keeps at least 64 sources so that staging it in LDS pays off.
-    const int target = 2048;
+    // About 2048 equal blocks (two full rounds at four 256-thread blocks per CU), twice
+    // that once there are many collocation tiles (finer chunks balance better there:
+    // measured 4-5% at 361x121 and 721x241, 3% slower at 181x61).  A chunk keeps at
+    // least 64 sources so that staging it in LDS pays off.
+    const int target = (ntiles >= 64) ? 2 * SW_PAIR_TARGET : SW_PAIR_TARGET;
     const int G = (target + ntiles / 2) / ntiles;
     return std::max(1, std::min(G, g.NM / 64));
 }
@@ -672,7 +686,8 @@ void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hi
         k_spline_setup<<<1, 1, 0, s>>>(g.M, g.bc, b.spl);
         k_spline<<<(2 * g.N + 127) / 128, 128, 0, s>>>(g, b.spl, b.psi, b.zeta, b.psiy, b.zetay);
     }
-    k_points<<<(g.NM + 255) / 256, 256, 0, s>>>(g, u, b.psi, b.zeta, b.psiy, b.zetay, b.src64,
+    k_points<<<(unsigned)((8 * (size_t)g.NM + 255) / 256), 256, 0, s>>>(
+        g, u, b.psi, b.zeta, b.psiy, b.zetay, b.src64,
                                                  b.src32, b.col, E);
 }
 }  // namespace

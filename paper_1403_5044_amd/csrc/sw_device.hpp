@@ -47,15 +47,29 @@ __device__ inline double grect(double A, double B, double C, double disc, double
     return a * lint(C, B, A, disc, b / a) + b * lint(A, B, C, disc, a / b);
 }
 
+// I = integral of the linearised kernel over the truncated domain plus its image.
+// The direct part is four quadrants about the collocation point (x lengths a1 behind,
+// a2 ahead; y lengths ys below, yM - ys above).  The image strip covers distances ys to
+// ys + yM below, so its lower quadrants extend the direct ones from ys to yM + ys: the
+// two lower direct quadrants cancel against the subtracted part of the image, leaving
+// four rectangles.  Term m of closed_form_I is grect(A, sB_m B, C, disc, a_m, b_m) with
+//   m = 0: (+, a2, yM - ys), 1: (-, a1, yM - ys), 2: (-, a2, yM + ys), 3: (+, a1, yM + ys).
 __device__ inline double closed_form_I(double A, double B, double C, double disc, double a1, double a2,
                                 double ys, double yM) {
-    const double b1 = ys, b2 = yM - ys;
-    const double direct = grect(A, B, C, disc, a2, b2) + grect(A, -B, C, disc, a1, b2) +
-                          grect(A, -B, C, disc, a2, b1) + grect(A, B, C, disc, a1, b1);
-    const double yt = yM + ys;
-    const double image = (grect(A, -B, C, disc, a2, yt) + grect(A, B, C, disc, a1, yt)) -
-                         (grect(A, -B, C, disc, a2, ys) + grect(A, B, C, disc, a1, ys));
-    return direct + image;
+    const double b2 = yM - ys, yt = yM + ys;
+    return (grect(A, B, C, disc, a2, b2) + grect(A, -B, C, disc, a1, b2)) +
+           (grect(A, -B, C, disc, a2, yt) + grect(A, B, C, disc, a1, yt));
+}
+
+// Half h (0 or 1) of rectangle term m of closed_form_I: grect's two log integrals
+// are split over two lanes.
+__device__ inline double closed_form_I_part(int m, int h, double A, double B, double C, double disc,
+                                            double a1, double a2, double ys, double yM) {
+    const double a = (m == 0 || m == 2) ? a2 : a1;
+    const double b = (m < 2) ? yM - ys : yM + ys;
+    const double sB = (m == 0 || m == 3) ? B : -B;
+    if (!(a > 0.0) || !(b > 0.0)) return 0.0;
+    return h == 0 ? a * lint(C, sB, A, disc, b / a) : b * lint(A, sB, C, disc, a / b);
 }
 
 // In-place inclusive prefix sum of arr[0..n) in LDS by one 64-lane wavefront

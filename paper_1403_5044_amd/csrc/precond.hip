@@ -757,13 +757,12 @@ struct GemmBatch {
 // FP64 matrix cores (v_mfma_f64_16x16x4f64): four wavefronts per workgroup in a 2 x 2
 // arrangement, each computing WM x WN MFMA tiles of 16 x 16 (a (32 WM) x (32 WN) tile of C
 // per workgroup; 64 x 64 for large blocks, 32 x 32 for N <= 256 so that small products
-// still fill the chip), K staged through LDS 16 at a time with the next slice prefetched
-// into registers.  Operand layout of the instruction: lane l holds A[l % 16][l / 16] and
+// still fill the chip), K staged through LDS kGK at a time with the next slice prefetched
+// into registers (64 for the small tiles: few, latency-bound K steps).  Operand layout of the instruction: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; result register r of lane l is C[l / 16 + 4 r][l % 16].
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kGK = 16;
 
-template <int WM, int WN>
+template <int WM, int WN, int kGK>
 __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch batch) {
     constexpr int TM = 32 * WM, TN = 32 * WN;
     constexpr int EA = TM * kGK / 256, EB = TN * kGK / 256;  // slice elements per thread
@@ -1050,10 +1049,10 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
         for (int i = 0; i < cnt; ++i) batch.j[i] = jobs[b + i];
         if (n <= 256) {
             dim3 grid((n + 31) / 32, (n + 31) / 32, cnt);
-            k_gemm<1, 1><<<grid, 256, 0, s>>>(n, alpha, batch);
+            k_gemm<1, 1, 64><<<grid, 256, 0, s>>>(n, alpha, batch);
         } else {
             dim3 grid((n + 63) / 64, (n + 63) / 64, cnt);
-            k_gemm<2, 2><<<grid, 256, 0, s>>>(n, alpha, batch);
+            k_gemm<2, 2, 16><<<grid, 256, 0, s>>>(n, alpha, batch);
         }
     }
 }

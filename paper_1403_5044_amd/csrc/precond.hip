@@ -274,37 +274,41 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 // ---- N <= 192: the whole block in registers, one workgroup ----
-// Wavefront 0 eliminates the panels (rows lane + 64 i in registers; pivot search by
-// DPP and readlane, no block barrier).  Wavefronts 1..7 hold the block: thread
-// (tr = t' / 32, tc = t' % 32), t' = t - 64, holds B[tr + 14 i][tc + 32 c].  Look-ahead:
-// the owners stage panel k+1's columns in LDS, all tile threads apply panel k to them
-// (one row each), and wavefront 0 eliminates panel k+1 while the others apply panel
-// k's rank-kPW update to the whole block.
+// Wavefront 0 eliminates the panels (rows lane + 64 i in registers; pivot search by DPP
+// and readlane, no block barrier inside a panel).  Wavefronts 1..7 hold the block: thread
+// (tr = t' / 32, tc = t' % 32), t' = t - 64, holds B[tr + 14 i][tc + 32 c].  The two roles
+// run separate loops whose barriers pair one to one (two per panel), so the block's
+// registers are not live in wavefront 0's code.  Iteration k:
+//   wavefront 0: applies panel k (its multipliers, kept in registers) to panel k+1's
+//     columns, which the tile waves staged before panel k's update; barrier E;
+//     eliminates panel k+1; barrier X.
+//   tile waves: copy panel k's pivot rows to Zr (their base becomes zero); barrier E;
+//     apply panel k's rank-kPW update to the whole block; stage panel k+2's columns;
+//     barrier X.
 constexpr int kGT = 512;
 constexpr int kPW = 8;
 
-// Eliminates the panel held in pv (rows lane + 64 i, columns k0 .. k0 + kb - 1) in place.
-template <int RW>
-__device__ __forceinline__ void gj_panel_wave(int k0, int kb, int lane, double (&pv)[RW][kPW],
-                                              int* rowpiv, int* step_of, unsigned& usedm,
-                                              int& zeros) {
+// Steps of one panel held in pv (rows lane + 64 i, columns 0..kb-1), in place.  A candidate
+// carries its row in the pivot key: (high word of |v|, low 8 bits cleared) | tag, tag =
+// 255 - row while the row is a candidate and -1 (key -1) once pivoted or padding.  One
+// integer maximum then yields the pivot row: the largest candidate to 12 mantissa bits
+// (partial pivoting needs a large pivot, not the exact maximum; a NaN is taken and
+// reported), the lowest row among ties.  Lane s of rps receives the pivot row of step s.
+template <int RW, bool FULL>
+__device__ __forceinline__ void gj_panel_steps(int kb, int lane, double (&pv)[RW][kPW],
+                                               int (&tag)[RW], int& rps, int& zeros) {
 #pragma unroll
     for (int s = 0; s < kPW; ++s) {
-        if (s >= kb) break;
-        int key = -1, bi = -1;
+        if (!FULL && s >= kb) break;
+        int key = -1;
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int kk = pivot_key(pv[i][s]);
-            if (!((usedm >> i) & 1u) && kk > key) {
-                key = kk;
-                bi = i;
-            }
+            const int hi = (int)((unsigned long long)__double_as_longlong(pv[i][s]) >> 32);
+            key = max(key, (hi & 0x7fffff00) | tag[i]);
         }
-        const int mx = wave_max_i32(key);
-        const unsigned long long mask = __ballot(bi >= 0 && key == mx);
-        const int pl = mask ? __builtin_ctzll(mask) : 0;
-        const int pi = max(0, __builtin_amdgcn_readlane(bi, pl));
-        const int rp = pl + 64 * pi;
+        const int wt = wave_max_i32(key) & 255;
+        const int rp = 255 - wt;
+        const int pl = rp & 63, pi = rp >> 6;
         double prow[kPW];
 #pragma unroll
         for (int u = 0; u < kPW; ++u) prow[u] = 0.0;
@@ -328,16 +332,67 @@ __device__ __forceinline__ void gj_panel_wave(int k0, int kb, int lane, double (
         if (lane == pl) {
 #pragma unroll
             for (int i = 0; i < RW; ++i)
-                if (i == pi) {
+                if (i == pi)
 #pragma unroll
                     for (int u = 0; u < kPW; ++u) pv[i][u] = pd[u];
-                    usedm |= 1u << i;
-                }
         }
-        if (lane == 0) {
-            rowpiv[k0 + s] = rp;
-            step_of[rp] = k0 + s;
-        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) tag[i] = (tag[i] == wt) ? -1 : tag[i];
+        rps = (lane == s) ? rp : rps;
+    }
+}
+
+// Eliminates panel k0 .. k0 + kb - 1 held in pv and records its pivots in rowpiv / step_of.
+template <int RW>
+__device__ __forceinline__ void gj_panel(int N, int k0, int kb, int lane, double (&pv)[RW][kPW],
+                                         int* rowpiv, int* step_of, int& zeros) {
+    int tag[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int r = lane + 64 * i;
+        tag[i] = (r < N && step_of[r] < 0) ? 255 - r : -1;
+    }
+    int rps = 0;
+    if (kb == kPW)
+        gj_panel_steps<RW, true>(kb, lane, pv, tag, rps, zeros);
+    else
+        gj_panel_steps<RW, false>(kb, lane, pv, tag, rps, zeros);
+    if (lane < kb) {
+        rowpiv[k0 + lane] = rps;
+        step_of[rps] = k0 + lane;
+    }
+}
+
+// Panel k (multipliers pk, pivot rows rowpiv[k0 ..]) applied to the next panel's columns
+// staged in Pin before panel k's update, for rows lane + 64 i: the base (zero on panel k's
+// pivot rows) plus the sum over t of multiplier t times the staged pivot row t.
+template <int RW, bool FULL>
+__device__ __forceinline__ void gj_stage(int lane, int k0, int kb, const double (&pk)[RW][kPW],
+                                         double (&pv)[RW][kPW], const double (*Pin)[kPW],
+                                         const int* rowpiv, const int* step_of) {
+    int r[kPW];
+#pragma unroll
+    for (int s = 0; s < kPW; ++s) r[s] = (FULL || s < kb) ? rowpiv[k0 + s] : 0;
+    bool pr[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int st = step_of[lane + 64 * i] - k0;
+        pr[i] = st >= 0 && st < kb;
+    }
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) pv[i][u] = pr[i] ? 0.0 : Pin[lane + 64 * i][u];
+#pragma unroll
+    for (int s = 0; s < kPW; ++s) {
+        if (!FULL && s >= kb) break;
+        double z[kPW];
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) z[u] = Pin[r[s]][u];
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int u = 0; u < kPW; ++u) pv[i][u] = fma(pk[i][s], z[u], pv[i][u]);
     }
 }
 
@@ -349,24 +404,11 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
     constexpr int RP = (R > 64 * RW) ? R : 64 * RW;  // rows of the panel buffers
     double* A = base + (size_t)blockIdx.x * stride;
     __shared__ double Pn[2][RP][kPW];  // eliminated panels k (k even / odd)
-    __shared__ double Pin[RP][kPW];    // panel columns staged for elimination
+    __shared__ double Pin[RP][kPW];    // next panel's columns, staged before the update
     __shared__ double Zr[kPW][C];      // pivot rows before the update
     __shared__ int rowpiv[C], step_of[RP];
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const bool w0 = t < 64;
-    const int tt = t - 64;  // tile thread
-    const int tc = tt & 31, tr = tt >> 5;
-    double a[RB][CB];
-    if (!w0) {
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int r = tr + 14 * i, j = tc + 32 * c;
-                a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
-            }
-    }
     for (int e = t; e < RP * kPW; e += kGT) {
         (&Pn[0][0][0])[e] = 0.0;
         (&Pn[1][0][0])[e] = 0.0;
@@ -374,40 +416,84 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
     }
     for (int r = t; r < RP; r += kGT) step_of[r] = -1;
     for (int r = t; r < C; r += kGT) rowpiv[r] = -1;
-    unsigned usedm = 0;  // wavefront 0: bit i marks row lane + 64 i as pivoted or padding
+    const int npan = (N + kPW - 1) / kPW;
+    if (__builtin_amdgcn_readfirstlane(t) < 64) {
+        // wavefront 0 (a uniform branch: each wavefront runs one of the two loops)
+        int zeros = 0;
+        double pk[RW][kPW];  // multipliers of the last eliminated panel
+        __syncthreads();     // B0: panel 0 staged
+        {
+            double pv[RW][kPW];
 #pragma unroll
-    for (int i = 0; i < RW; ++i)
-        if (lane + 64 * i >= N) usedm |= 1u << i;
-    int zeros = 0;
-    __syncthreads();
-    // panel 0 columns
-    if (!w0 && tc < kPW) {
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) pv[i][u] = Pin[lane + 64 * i][u];
+            __syncthreads();  // B1: Pin free for panel 1
+            gj_panel<RW>(N, 0, min(kPW, N), lane, pv, rowpiv, step_of, zeros);
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int u = 0; u < kPW; ++u) {
+                    Pn[0][lane + 64 * i][u] = pv[i][u];
+                    pk[i][u] = pv[i][u];
+                }
+        }
+        __syncthreads();  // X(-1)
+        for (int k = 0; k < npan; ++k) {
+            const int k0 = k * kPW, kb = min(kPW, N - k0);
+            const int k1 = k0 + kPW, kb1 = min(kPW, N - k1);
+            double pv[RW][kPW];
+            if (k + 1 < npan) {
+                if (kb == kPW)
+                    gj_stage<RW, true>(lane, k0, kb, pk, pv, Pin, rowpiv, step_of);
+                else
+                    gj_stage<RW, false>(lane, k0, kb, pk, pv, Pin, rowpiv, step_of);
+            }
+            __syncthreads();  // E(k)
+            if (k + 1 < npan) {
+                gj_panel<RW>(N, k1, kb1, lane, pv, rowpiv, step_of, zeros);
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int u = 0; u < kPW; ++u) {
+                        Pn[(k + 1) & 1][lane + 64 * i][u] = pv[i][u];
+                        pk[i][u] = pv[i][u];
+                    }
+            }
+            __syncthreads();  // X(k)
+        }
+        if (t == 0 && info) info[blockIdx.x] = zeros;
+        return;
+    }
+    const int tt = t - 64;  // tile thread
+    const int tc = tt & 31, tr = tt >> 5;
+    double a[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int r = tr + 14 * i, j = tc + 32 * c;
+            a[i][c] = (r < N && j < N) ? A[(size_t)r * N + j] : 0.0;
+        }
+    if (tc < kPW) {
 #pragma unroll
         for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc] = a[i][0];
     }
-    __syncthreads();
-    if (w0) {
-        double pv[RW][kPW];
+    __syncthreads();  // B0
+    __syncthreads();  // B1
+    if (npan > 1 && tc >= kPW && tc < 2 * kPW) {
 #pragma unroll
-        for (int i = 0; i < RW; ++i)
-#pragma unroll
-            for (int u = 0; u < kPW; ++u) pv[i][u] = Pin[lane + 64 * i][u];
-        gj_panel_wave<RW>(0, min(kPW, N), lane, pv, rowpiv, step_of, usedm, zeros);
-#pragma unroll
-        for (int i = 0; i < RW; ++i)
-#pragma unroll
-            for (int u = 0; u < kPW; ++u) Pn[0][lane + 64 * i][u] = pv[i][u];
+        for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc - kPW] = a[i][0];
     }
-    __syncthreads();
-    const int npan = (N + kPW - 1) / kPW;
+    __syncthreads();  // X(-1)
     for (int k = 0; k < npan; ++k) {
         const int k0 = k * kPW, kb = min(kPW, N - k0);
         const int buf = k & 1;
         const int c0 = k0 >> 5, t0 = k0 & 31;  // kPW divides 32: a panel never straddles c
-        const int k1 = k0 + kPW, kb1 = min(kPW, N - k1);
-        const int c1 = k1 >> 5, t1 = k1 & 31;
-        if (!w0) {
-            // pivot rows of panel k to Zr; their base becomes zero
+        const int k2 = k0 + 2 * kPW;
+        const int c2 = k2 >> 5, t2 = k2 & 31;
+        {
+            // panel k's pivot rows to Zr; their base becomes zero
             int st[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) st[i] = step_of[tr + 14 * i] - k0;
@@ -421,49 +507,9 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
                     }
                 }
             }
-            // panel k+1's columns as they stand before panel k's update
-            if (k + 1 < npan && tc >= t1 && tc < t1 + kPW) {
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c == c1)
-#pragma unroll
-                        for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc - t1] = a[i][c];
-            }
         }
-        __syncthreads();
-        if (!w0 && k + 1 < npan && tt < RP) {
-            // panel k applied to the staged columns, one row per thread
-            double pr[kPW], v[kPW];
-#pragma unroll
-            for (int u = 0; u < kPW; ++u) {
-                pr[u] = Pn[buf][tt][u];
-                v[u] = Pin[tt][u];
-            }
-#pragma unroll
-            for (int tt2 = 0; tt2 < kPW; ++tt2) {
-                if (tt2 >= kb) break;
-#pragma unroll
-                for (int u = 0; u < kPW; ++u) v[u] = fma(pr[tt2], Zr[tt2][k1 + u], v[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < kPW; ++u) Pin[tt][u] = v[u];
-        }
-        __syncthreads();
-        if (w0) {
-            if (k + 1 < npan) {
-                // panel k+1 eliminated
-                double pv[RW][kPW];
-#pragma unroll
-                for (int i = 0; i < RW; ++i)
-#pragma unroll
-                    for (int u = 0; u < kPW; ++u) pv[i][u] = Pin[lane + 64 * i][u];
-                gj_panel_wave<RW>(k1, kb1, lane, pv, rowpiv, step_of, usedm, zeros);
-#pragma unroll
-                for (int i = 0; i < RW; ++i)
-#pragma unroll
-                    for (int u = 0; u < kPW; ++u) Pn[buf ^ 1][lane + 64 * i][u] = pv[i][u];
-            }
-        } else {
+        __syncthreads();  // E(k)
+        {
             // rank-kb update of the whole block, operands of step u + 1 loaded while u is applied
             double z[CB], p[RB];
 #pragma unroll
@@ -496,22 +542,27 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 #pragma unroll
                         for (int i = 0; i < RB; ++i) a[i][c] = Pn[buf][tr + 14 * i][tc - t0];
             }
-        }
-        __syncthreads();
-    }
-    if (!w0) {
+            // panel k+2's columns, before panel k+1's update
+            if (k2 < N && tc >= t2 && tc < t2 + kPW) {
 #pragma unroll
-        for (int i = 0; i < RB; ++i)
+                for (int c = 0; c < CB; ++c)
+                    if (c == c2)
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int r = tr + 14 * i, j = tc + 32 * c;
-                if (r < N && j < N) {
-                    const int sr = step_of[r], pj = rowpiv[j];
-                    if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
-                }
+                        for (int i = 0; i < RB; ++i) Pin[tr + 14 * i][tc - t2] = a[i][c];
             }
+        }
+        __syncthreads();  // X(k)
     }
-    if (t == 0 && info) info[blockIdx.x] = zeros;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int r = tr + 14 * i, j = tc + 32 * c;
+            if (r < N && j < N) {
+                const int sr = step_of[r], pj = rowpiv[j];
+                if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
+            }
+        }
 }
 
 // ---- N > 192: the block in global memory, one panel and one update launch per panel ----
@@ -720,6 +771,8 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
         k_gj_tile<5, 2, 1><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 128) {
         k_gj_tile<10, 4, 2><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
+    } else if (N <= 182) {
+        k_gj_tile<13, 6, 3><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else if (N <= 192) {
         k_gj_tile<14, 6, 3><<<nblocks, kGT, 0, s>>>(N, base, stride, info);
     } else {

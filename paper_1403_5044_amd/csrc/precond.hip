@@ -553,16 +553,34 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
         }
         __syncthreads();  // X(k)
     }
+    // The inverse: row step_of[r], column rowpiv[j] takes B[r][j].  Output column o comes
+    // from column step_of[o]; each half-wave passes its row through LDS (the panel buffers
+    // are free now) and reads it back permuted, so that its stores are contiguous.
+    static_assert(14 * C <= 2 * RP * kPW, "row buffers exceed the panel buffers");
+    double* rowbuf = &Pn[0][0][0] + (size_t)tr * C;
+    int src[CB];
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+    for (int c = 0; c < CB; ++c) {
+        const int o = tc + 32 * c;
+        src[c] = (o < N) ? step_of[o] : -1;
+    }
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int r = tr + 14 * i, j = tc + 32 * c;
-            if (r < N && j < N) {
-                const int sr = step_of[r], pj = rowpiv[j];
-                if (sr >= 0 && sr < N && pj >= 0 && pj < N) A[(size_t)sr * N + pj] = a[i][c];
+    for (int i = 0; i < RB; ++i) {
+        const int r = tr + 14 * i;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) rowbuf[tc + 32 * c] = a[i][c];
+        double v[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) v[c] = (src[c] >= 0 && src[c] < N) ? rowbuf[src[c]] : 0.0;
+        const int sr = (r < N) ? step_of[r] : -1;
+        if (sr >= 0 && sr < N) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int o = tc + 32 * c;
+                if (src[c] >= 0 && src[c] < N) A[(size_t)sr * N + o] = v[c];
             }
         }
+    }
 }
 
 // ---- N > 192: the block in global memory, one panel and one update launch per panel ----
@@ -741,11 +759,12 @@ __global__ void k_gjp_scatter(int N, const double* __restrict__ base, size_t str
     const int* step_of = w.piv + (size_t)blockIdx.y * 2 * N;
     const int* rowpiv = step_of + N;
     const size_t NN = (size_t)N * N;
+    // output (o, p) = B[rowpiv[o]][step_of[p]]: contiguous stores, gathered loads
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < NN;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
-        const int sr = step_of[r], pc = rowpiv[c];
-        if (sr >= 0 && sr < N && pc >= 0 && pc < N) O[(size_t)sr * N + pc] = B[e];
+        const int o = (int)(e / N), p = (int)(e - (size_t)o * N);
+        const int r = rowpiv[o], c = step_of[p];
+        if (r >= 0 && r < N && c >= 0 && c < N) O[e] = B[(size_t)r * N + c];
     }
 }
 

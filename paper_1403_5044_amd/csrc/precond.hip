@@ -288,53 +288,56 @@ __device__ __forceinline__ double rcp64(double x) {
 constexpr int kGT = 512;
 constexpr int kPW = 8;
 
-// Steps of one panel held in pv (rows lane + 64 i, columns 0..kb-1), in place.  A candidate
-// carries its row in the pivot key: (high word of |v|, low 8 bits cleared) | tag, tag =
-// 255 - row while the row is a candidate and -1 (key -1) once pivoted or padding.  One
-// integer maximum then yields the pivot row: the largest candidate to 12 mantissa bits
-// (partial pivoting needs a large pivot, not the exact maximum; a NaN is taken and
-// reported), the lowest row among ties.  Lane s of rps receives the pivot row of step s.
-template <int RW, bool FULL>
-__device__ __forceinline__ void gj_panel_steps(int kb, int lane, double (&pv)[RW][kPW],
+// Steps of one W-column panel held in pv (rows lane + 64 i, columns 0..kb-1), in place.  A
+// candidate carries its row in the pivot key: (high word of |v|, low TB bits cleared) |
+// tag, tag = 2^TB - 1 - row while the row is a candidate and -1 (key -1) once pivoted or
+// padding (64 RW <= 2^TB).  One integer maximum then yields the pivot row: the largest
+// candidate to 20 - TB mantissa bits (partial pivoting needs a large pivot, not the exact
+// maximum; a NaN is taken and reported), the lowest row among ties.  Lane s of rps
+// receives the pivot row of step s.
+template <int RW, int W, int TB, bool FULL>
+__device__ __forceinline__ void gj_panel_steps(int kb, int lane, double (&pv)[RW][W],
                                                int (&tag)[RW], int& rps, int& zeros) {
+    static_assert(64 * RW <= (1 << TB), "row tags need TB bits");
+    constexpr int kTagMask = (1 << TB) - 1;
 #pragma unroll
-    for (int s = 0; s < kPW; ++s) {
-        if (!FULL && s >= kb) break;
+    for (int s = 0; s < W; ++s) {
+        if (!FULL && s >= kb) continue;  // uniform; a constant trip count unrolls fully
         int key = -1;
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const int hi = (int)((unsigned long long)__double_as_longlong(pv[i][s]) >> 32);
-            key = max(key, (hi & 0x7fffff00) | tag[i]);
+            key = max(key, (hi & (0x7fffffff & ~kTagMask)) | tag[i]);
         }
-        const int wt = wave_max_i32(key) & 255;
-        const int rp = 255 - wt;
+        const int wt = wave_max_i32(key) & kTagMask;
+        const int rp = kTagMask - wt;
         const int pl = rp & 63, pi = rp >> 6;
-        double prow[kPW];
+        double prow[W];
 #pragma unroll
-        for (int u = 0; u < kPW; ++u) prow[u] = 0.0;
+        for (int u = 0; u < W; ++u) prow[u] = 0.0;
 #pragma unroll
         for (int i = 0; i < RW; ++i)
             if (i == pi)
 #pragma unroll
-                for (int u = 0; u < kPW; ++u) prow[u] = readlane_f64(pv[i][u], pl);
+                for (int u = 0; u < W; ++u) prow[u] = readlane_f64(pv[i][u], pl);
         const double piv = prow[s];
         if (!(fabs(piv) > 0.0)) ++zeros;
         const double d = rcp64(piv);
-        double pd[kPW];
+        double pd[W];
 #pragma unroll
-        for (int u = 0; u < kPW; ++u) pd[u] = (u == s) ? d : prow[u] * d;
+        for (int u = 0; u < W; ++u) pd[u] = (u == s) ? d : prow[u] * d;
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const double m = pv[i][s];
 #pragma unroll
-            for (int u = 0; u < kPW; ++u) pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
+            for (int u = 0; u < W; ++u) pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
         }
         if (lane == pl) {
 #pragma unroll
             for (int i = 0; i < RW; ++i)
                 if (i == pi)
 #pragma unroll
-                    for (int u = 0; u < kPW; ++u) pv[i][u] = pd[u];
+                    for (int u = 0; u < W; ++u) pv[i][u] = pd[u];
         }
 #pragma unroll
         for (int i = 0; i < RW; ++i) tag[i] = (tag[i] == wt) ? -1 : tag[i];
@@ -354,9 +357,9 @@ __device__ __forceinline__ void gj_panel(int N, int k0, int kb, int lane, double
     }
     int rps = 0;
     if (kb == kPW)
-        gj_panel_steps<RW, true>(kb, lane, pv, tag, rps, zeros);
+        gj_panel_steps<RW, kPW, 8, true>(kb, lane, pv, tag, rps, zeros);
     else
-        gj_panel_steps<RW, false>(kb, lane, pv, tag, rps, zeros);
+        gj_panel_steps<RW, kPW, 8, false>(kb, lane, pv, tag, rps, zeros);
     if (lane < kb) {
         rowpiv[k0 + lane] = rps;
         step_of[rps] = k0 + lane;
@@ -705,6 +708,65 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
 
+// Panel kernel for N <= 256: wavefront 0 holds panel rows lane + 64 i (i < RW) and takes
+// the steps without block barriers (the register-tile kernel's pivot steps, 16 columns);
+// then all 256 threads copy the old pivot rows.  Same outputs as k_gjp_panel.
+template <int RW>
+__global__ __launch_bounds__(kGP) void k_gjp_panel1(int N, const double* __restrict__ base,
+                                                    size_t stride, GjWork w, int k0,
+                                                    int* __restrict__ info) {
+    const double* B = base + (size_t)blockIdx.x * stride;
+    double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
+    double* z = w.z + (size_t)blockIdx.x * kPWG * N;
+    int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
+    int* rowpiv = step_of + N;
+    __shared__ int rp_s[kPWG];
+    const int t = threadIdx.x;
+    const int kb = min(kPWG, N - k0);
+    if (__builtin_amdgcn_readfirstlane(t) < 64) {
+        const int lane = t;
+        double pv[RW][kPWG];
+        int tag[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int r = lane + 64 * i;
+            const bool valid = r < N;
+            const int st = valid ? ((k0 > 0) ? step_of[r] : -1) : N;
+            tag[i] = (valid && st < 0) ? 511 - r : -1;
+#pragma unroll
+            for (int u = 0; u < kPWG; ++u)
+                pv[i][u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
+        }
+        int zeros = 0, rps = 0;
+        if (kb == kPWG)
+            gj_panel_steps<RW, kPWG, 9, true>(kb, lane, pv, tag, rps, zeros);
+        else
+            gj_panel_steps<RW, kPWG, 9, false>(kb, lane, pv, tag, rps, zeros);
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int r = lane + 64 * i;
+            if (r < N) {
+#pragma unroll
+                for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[i][u];
+                if (k0 == 0) step_of[r] = -1;
+            }
+        }
+        // the -1 marks above reach memory before this panel's steps are written
+        __threadfence();
+        if (lane < kb) {
+            rowpiv[k0 + lane] = rps;
+            step_of[rps] = k0 + lane;
+            rp_s[lane] = rps;
+        }
+        if (lane == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
+    }
+    __syncthreads();
+    for (int e = t; e < kb * N; e += kGP) {
+        const int tt = e / N, j = e - tt * N;
+        z[(size_t)tt * N + j] = B[(size_t)rp_s[tt] * N + j];
+    }
+}
+
 // Rank-kb update of every column outside the panel; the panel columns take pn.
 // Tile of 16 rows x 64 columns per 256-thread workgroup; grid (cols, rows, blocks).
 __global__ __launch_bounds__(256) void k_gjp_update(int N, double* __restrict__ base,
@@ -802,7 +864,9 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
         w.piv = reinterpret_cast<int*>(work + (size_t)nblocks * 2 * kPWG * N);
         const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
         for (int k0 = 0; k0 < N; k0 += kPWG) {
-            if (N <= 2 * kGP)
+            if (N <= 256)
+                k_gjp_panel1<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+            else if (N <= 2 * kGP)
                 k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
             else
                 k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);

@@ -878,7 +878,8 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
     }
 }
 // C = Cin + alpha A B for N x N row-major blocks (C may equal Cin, not A or B);
-// blockIdx.z selects one of a list of such products.
+// blockIdx.z selects one of a list of such products.  A job with B = nullptr copies A
+// to C instead.
 struct GemmJob {
     const double* A;
     const double* B;
@@ -905,6 +906,15 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
     const GemmJob job = batch.j[blockIdx.z];
     const double* __restrict__ A = job.A;
     const double* __restrict__ B = job.B;
+    if (B == nullptr) {
+        // a copy job (C = A over this block's tile), riding along with the products
+        const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
+        for (int e = threadIdx.x; e < TM * TN; e += 256) {
+            const int gr = r0 + e / TN, gc = c0 + e % TN;
+            if (gr < n && gc < n) job.C[(size_t)gr * n + gc] = A[(size_t)gr * n + gc];
+        }
+        return;
+    }
     __shared__ double As[TM][kGK + 1];
     __shared__ double Bs[kGK][TN + 2];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -1197,9 +1207,10 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
 }  // namespace
 
 namespace {
-// scratch blocks: q products per factorisation step, or M inverses at once (q = 0, N > 192)
+// scratch blocks: the inversion's output block (N > 192) and two halves of 2q products
+// (factorisation steps of either parity), or M inverses at once (q = 0, N > 192)
 size_t tmp2_blocks(const Geo& g, int q) {
-    return (size_t)std::max({2 * q, 1, (q == 0 && g.N > 192) ? g.M : 1});
+    return (size_t)std::max({4 * q + 1, 1, (q == 0 && g.N > 192) ? g.M : 1});
 }
 
 // workspace of the diagonal-block inversion (N > 192), at least one N x N block
@@ -1489,42 +1500,45 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         if (q == 0) {
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
         } else {
-            double* scratchL = P->tmp2;  // 2q blocks: L_{i,l}, then G_{l,j}
+            // Step l: Dinv_l; L_{i,l} = S_{i,l} Dinv_l and G_{l,j} = Dinv_l U_{l,j} into the
+            // scratch half of l's parity; S_{i,j} -= S_{i,l} G_{l,j}.  G replaces U_{l,j} in the
+            // same launch as the Schur update (which does not read U); L replaces S_{i,l} in
+            // the next step's first launch (the Schur update reads S_{i,l}).
+            double* gjt = P->tmp2;  // output block of an N > 192 inversion
+            auto half = [&](int l) { return P->tmp2 + NN * (1 + (size_t)(l & 1) * 2 * q); };
+            std::vector<GemmJob> pendingL;
             for (int l = 0; l < g.M; ++l) {
-                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, P->tmp2, P->tmp,
-                           s);
+                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, gjt, P->tmp, s);
                 const int hi = std::min(g.M - 1, l + q);
                 const int cnt = hi - l;
                 if (cnt == 0) continue;
-                // L_{i,l} = S_{i,l} Dinv_l and G_{l,j} = Dinv_l U_{l,j} into scratch
-                std::vector<GemmJob> jobs;
+                double* sc = half(l);
+                std::vector<GemmJob> jobs = pendingL;
+                pendingL.clear();
                 for (int i = l + 1; i <= hi; ++i)
                     jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
                                            P->S + blk_off(P, l, q), nullptr,
-                                           scratchL + (size_t)(i - l - 1) * NN});
+                                           sc + (size_t)(i - l - 1) * NN});
                 for (int j = l + 1; j <= hi; ++j)
                     jobs.push_back(GemmJob{P->S + blk_off(P, l, q), P->S + blk_off(P, l, j - l + q),
-                                           nullptr, scratchL + (size_t)(q + j - l - 1) * NN});
+                                           nullptr, sc + (size_t)(q + j - l - 1) * NN});
                 gemm_batched(g.N, 1.0, jobs, s);
-                // S_{i,j} -= L_{i,l} U_{l,j}
                 jobs.clear();
                 for (int i = l + 1; i <= hi; ++i)
                     for (int j = l + 1; j <= hi; ++j) {
                         double* Sij = P->S + blk_off(P, i, j - i + q);
-                        jobs.push_back(GemmJob{scratchL + (size_t)(i - l - 1) * NN,
-                                               P->S + blk_off(P, l, j - l + q), Sij, Sij});
+                        jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
+                                               sc + (size_t)(q + j - l - 1) * NN, Sij, Sij});
                     }
-                gemm_batched(g.N, -1.0, jobs, s);
-                // L and G replace S_{i,l} and U_{l,j}
-                std::vector<FillJob> back;
-                for (int i = l + 1; i <= hi; ++i)
-                    back.push_back(FillJob{P->S + blk_off(P, i, l - i + q),
-                                           scratchL + (size_t)(i - l - 1) * NN, 2, 0});
                 for (int j = l + 1; j <= hi; ++j)
-                    back.push_back(FillJob{P->S + blk_off(P, l, j - l + q),
-                                           scratchL + (size_t)(q + j - l - 1) * NN, 2, 0});
-                fill_batched(g.N, back, s);
+                    jobs.push_back(GemmJob{sc + (size_t)(q + j - l - 1) * NN, nullptr, nullptr,
+                                           P->S + blk_off(P, l, j - l + q)});
+                gemm_batched(g.N, -1.0, jobs, s);
+                for (int i = l + 1; i <= hi; ++i)
+                    pendingL.push_back(GemmJob{sc + (size_t)(i - l - 1) * NN, nullptr, nullptr,
+                                               P->S + blk_off(P, i, l - i + q)});
             }
+            if (!pendingL.empty()) gemm_batched(g.N, 1.0, pendingL, s);
         }
         if (q > 0 && P->sb > 1) {
             build_super(P, plan, s);

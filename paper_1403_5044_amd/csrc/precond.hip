@@ -893,10 +893,10 @@ struct GemmBatch {
 
 // FP64 matrix cores (v_mfma_f64_16x16x4f64): four wavefronts per workgroup in a 2 x 2
 // arrangement, each computing WM x WN MFMA tiles of 16 x 16 (a (32 WM) x (32 WN) tile of C
-// per workgroup; 64 x 64 for large blocks, 32 x 32 for N <= 256 so that small products
-// still fill the chip), K staged through LDS kGK at a time with the next slice prefetched
-// into registers (64 for the small tiles: few, latency-bound K steps).  Operand layout of the instruction: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; result register r of lane l is C[l / 16 + 4 r][l % 16].
+// per workgroup; 64 x 64 for blocks with N > 256), K staged through LDS kGK at a time with
+// the next slice prefetched into registers.  Operand layout of the instruction: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// C[l / 16 + 4 r][l % 16].
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int WM, int WN, int kGK>
@@ -981,6 +981,73 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
 }
 
 
+
+// Small blocks (N <= 256): one 32 x 32 output tile per 256-thread workgroup.  The four
+// wavefronts take interleaved quarters of K (wavefront w: k-steps of 4 numbered w, w + 4,
+// ...; KS steps each, 16 KS >= n), load all their MFMA operands straight from global
+// memory first (one memory round trip instead of a staged K loop), accumulate 2 x 2
+// v_mfma_f64_16x16x4f64 tiles, and the four partial tiles are added in LDS in a fixed
+// order.  A job with B = nullptr copies A to C over the tile.
+template <int KS>
+__global__ __launch_bounds__(256) void k_gemm_ks(int n, double alpha, GemmBatch batch) {
+    const GemmJob job = batch.j[blockIdx.z];
+    const double* __restrict__ A = job.A;
+    const double* __restrict__ B = job.B;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    if (B == nullptr) {
+        for (int e = t; e < 32 * 32; e += 256) {
+            const int gr = r0 + (e >> 5), gc = c0 + (e & 31);
+            if (gr < n && gc < n) job.C[(size_t)gr * n + gc] = A[(size_t)gr * n + gc];
+        }
+        return;
+    }
+    __shared__ double part[4][32][33];
+    const int kl = lane >> 4, l16 = lane & 15;
+    const int nsteps = (n + 3) >> 2;
+    double fa[KS][2], fb[KS][2];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        const int k = 4 * (w + 4 * i) + kl;
+        const bool ok = k < n;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ar = r0 + 16 * h + l16, bc = c0 + 16 * h + l16;
+            fa[i][h] = (ok && ar < n) ? A[(size_t)ar * n + k] : 0.0;
+            fb[i][h] = (ok && bc < n) ? B[(size_t)k * n + bc] : 0.0;
+        }
+    }
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+        if (w + 4 * i < nsteps) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][a], fb[i][b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[w][16 * a + kl + 4 * r][16 * b + l16] = acc[a][b][r];
+    __syncthreads();
+    for (int e = t; e < 32 * 32; e += 256) {
+        const int row = e >> 5, col = e & 31;
+        const int gr = r0 + row, gc = c0 + col;
+        if (gr < n && gc < n) {
+            const double v = (part[0][row][col] + part[1][row][col]) + (part[2][row][col] + part[3][row][col]);
+            const size_t o = (size_t)gr * n + gc;
+            job.C[o] = (job.Cin ? job.Cin[o] : 0.0) + alpha * v;
+        }
+    }
+}
 
 // ---- apply ----------------------------------------------------------------------------
 // One 64-lane workgroup per row l; the row lives in LDS.  Both sequential
@@ -1195,7 +1262,10 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
         for (int i = 0; i < cnt; ++i) batch.j[i] = jobs[b + i];
         if (n <= 256) {
             dim3 grid((n + 31) / 32, (n + 31) / 32, cnt);
-            k_gemm<1, 1, 64><<<grid, 256, 0, s>>>(n, alpha, batch);
+            if (n <= 192)
+                k_gemm_ks<12><<<grid, 256, 0, s>>>(n, alpha, batch);
+            else
+                k_gemm_ks<16><<<grid, 256, 0, s>>>(n, alpha, batch);
         } else {
             dim3 grid((n + 63) / 64, (n + 63) / 64, cnt);
             k_gemm<2, 2, 16><<<grid, 256, 0, s>>>(n, alpha, batch);

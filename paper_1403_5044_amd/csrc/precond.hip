@@ -80,55 +80,37 @@ __device__ __forceinline__ double rsq_exact(double x) {
     return fma(0.5 * y, e, y);
 }
 
-// A-hat^{-1} b in place along a strided vector: row r >= 1 gives x_r = 2 b_r - x_{r-1};
-// row 0 then gives x_0 = (b_0 - 2 a01 b_1) / (a00 - a01).
-__device__ void ahat_solve(const Geo& g, const double* b, double* x, size_t stride) {
-    const double a01 = g.x1 / g.dx;
-    const double a00 = g.nu - a01;
-    double prev = (b[0] - 2.0 * a01 * b[stride]) / (a00 - a01);
-    x[0] = prev;
-    for (int r = 1; r < g.N; ++r) {
-        prev = 2.0 * b[(size_t)r * stride] - prev;
-        x[(size_t)r * stride] = prev;
-    }
-}
-
-// out = T v (out_0 = 0): trapezoid integration of v from z_0 = -(x_1/nu) v_0, then
-// averages of neighbouring grid values.
-__device__ void apply_T(const Geo& g, const double* v, double* out, size_t stride, double scale) {
-    const double hdx = 0.5 * g.dx;
-    double z = (-g.x1 / g.nu) * v[0];
-    double vp = v[0];
-    out[0] = 0.0;
-    for (int r = 1; r < g.N; ++r) {
-        const double vr = v[(size_t)r * stride];
-        const double zn = z + hdx * (vp + vr);
-        out[(size_t)r * stride] = scale * 0.5 * (z + zn);
-        z = zn;
-        vp = vr;
-    }
-}
-
-// Wc[:, n] = (2 pi / F^2) T A-hat^{-1} T e_n; one thread per column, scratch X [N][N].
-__global__ void k_wmat(Geo g, double* __restrict__ X, double* __restrict__ Wc) {
+// Wc[:, n] = (2 pi / F^2) T A-hat^{-1} T e_n; one thread per column.  The three sweeps
+// down the column are recurrences and run together in registers:
+//   t = T e_n:        z_0 = -(x_1/nu) [n = 0], z_r = z_{r-1} + dx/2 (e_{r-1} + e_r),
+//                     t_0 = 0, t_r = (z_{r-1} + z_r)/2;
+//   s = A-hat^{-1} t: s_0 = (t_0 - 2 a01 t_1) / (a00 - a01), s_r = 2 t_r - s_{r-1};
+//   w = T s:          the same trapezoid recurrence on s, from -(x_1/nu) s_0.
+__global__ void k_wmat(Geo g, double* __restrict__ Wc) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
-    const size_t st = g.N;
-    // X[:, n] = T e_n
-    {
-        const double hdx = 0.5 * g.dx;
-        double z = (n == 0) ? (-g.x1 / g.nu) : 0.0;
-        X[n] = 0.0;
-        for (int r = 1; r < g.N; ++r) {
-            const double vp = (r - 1 == n) ? 1.0 : 0.0;
-            const double vr = (r == n) ? 1.0 : 0.0;
-            const double zn = z + hdx * (vp + vr);
-            X[(size_t)r * st + n] = 0.5 * (z + zn);
-            z = zn;
-        }
+    const int N = g.N;
+    const double hdx = 0.5 * g.dx;
+    const double a01 = g.x1 / g.dx, a00 = g.nu - a01;
+    const double scale = kTwoPi / (g.F * g.F);
+    auto e = [n](int r) { return (r == n) ? 1.0 : 0.0; };
+    // t_0 = 0 and t_1 from the first step of the T recurrence
+    double z1 = (n == 0) ? (-g.x1 / g.nu) : 0.0;
+    const double t1 = 0.5 * (z1 + (z1 + hdx * (e(0) + e(1))));
+    // s_0 = (t_0 - 2 a01 t_1) / (a00 - a01), then s_r = 2 t_r - s_{r-1}
+    double sp = (0.0 - 2.0 * a01 * t1) / (a00 - a01);
+    double z3 = (-g.x1 / g.nu) * sp;
+    Wc[n] = 0.0;
+    for (int r = 1; r < N; ++r) {
+        const double z1n = z1 + hdx * (e(r - 1) + e(r));
+        const double t = 0.5 * (z1 + z1n);
+        z1 = z1n;
+        const double sr = 2.0 * t - sp;
+        const double z3n = z3 + hdx * (sp + sr);
+        Wc[(size_t)r * N + n] = scale * 0.5 * (z3 + z3n);
+        z3 = z3n;
+        sp = sr;
     }
-    ahat_solve(g, X + n, X + n, st);
-    apply_T(g, X + n, Wc + n, st, kTwoPi / (g.F * g.F));
 }
 
 // sum_{i,j} w(i,j) K3(i,j; k,l) for each collocation point, split over row chunks.
@@ -167,6 +149,8 @@ __global__ void k_k3_final(Geo g, int G, const double* __restrict__ part, double
 }
 
 // Entries of the banded Schur complement before factorisation.
+// One workgroup per 16 rows of one band block (l, d): grid (M nb, ceil(N / 16)),
+// threads over the columns n.
 __global__ __launch_bounds__(256) void k_assemble(Geo g, int q, const double* __restrict__ k3,
                                                   const double* __restrict__ Wc,
                                                   double* __restrict__ S) {
@@ -1510,7 +1494,7 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const size_t nw = plan_super(g, q, super_rows(g, q)).nblocks;
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
                        gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4,
-                       (size_t)G * g.ncol * 8, NN * 8, nw * NN * 8});
+                       (size_t)G * g.ncol * 8, nw * NN * 8});
 }
 
 size_t precond_bytes(const sw_precond* P) { return P ? P->bytes : 0; }
@@ -1555,12 +1539,11 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->tmp2 = c.take<double>(tmp2_blocks(g, q) * NN);
     P->info = c.take<int>(g.M);
     double* part = c.take<double>((size_t)G * g.ncol);
-    double* X = c.take<double>(NN);
     const SuperPlan plan = plan_super(g, q, super_rows(g, q));
     P->sb = plan.b;
     P->W = c.take<double>(plan.nblocks * NN);
     try {
-        k_wmat<<<(g.N + 63) / 64, 64, 0, s>>>(g, X, P->Wc);
+        k_wmat<<<(g.N + 63) / 64, 64, 0, s>>>(g, P->Wc);
         const int ntile = (g.ncol + 255) / 256;
         k_k3_partial<<<ntile * G, 256, 0, s>>>(g, G, part);
         k_k3_final<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, G, part, P->k3);

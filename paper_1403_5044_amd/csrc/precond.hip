@@ -582,7 +582,7 @@ constexpr int kPWG = 16;
 
 struct GjWork {
     double* pn;   // [nblocks][N][kPWG]
-    double* z;    // [nblocks][kPWG][N]
+    double* z;    // [nblocks][kPWG][N]; for N <= 256 the second Pn buffer, [nblocks][N][kPWG]
     int* piv;     // [nblocks][2][N]: step_of, rowpiv
 };
 
@@ -692,62 +692,105 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
 
-// Panel kernel for N <= 256: wavefront 0 holds panel rows lane + 64 i (i < RW) and takes
-// the steps without block barriers (the register-tile kernel's pivot steps, 16 columns);
-// then all 256 threads copy the old pivot rows.  Same outputs as k_gjp_panel.
-template <int RW>
-__global__ __launch_bounds__(kGP) void k_gjp_panel1(int N, const double* __restrict__ base,
-                                                    size_t stride, GjWork w, int k0,
-                                                    int* __restrict__ info) {
-    const double* B = base + (size_t)blockIdx.x * stride;
-    double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
-    double* z = w.z + (size_t)blockIdx.x * kPWG * N;
-    int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
+// ---- 192 < N <= 256: one launch per panel, column strips ----
+// Launch k (k = -1 .. npan - 1): workgroup s owns columns [16 s, 16 s + 16) of every row,
+// one row per thread.  If panel k exists (first column kp), the workgroup applies it to
+// its strip, B[r] <- base_r + sum_t Pn_k[r][t] Z_t with base_r = 0 on panel k's pivot
+// rows (panel k's own strip takes Pn_k), reading the old pivot rows Z_t of its strip
+// before any of its writes: no other workgroup touches these columns, so no copy of the
+// pivot rows is needed.  The workgroup holding panel k+1 (first column kn) then
+// eliminates it from its updated strip (wavefront 0, rows lane + 64 i, the register-tile
+// pivot steps) and writes Pn_{k+1} and the pivots; Pn alternates between two buffers by
+// panel parity.  It does not store its strip: launch k+1 gives those columns Pn_{k+1}.
+__global__ __launch_bounds__(kGP) void k_gjs_step(int N, double* __restrict__ base, size_t stride,
+                                                  GjWork w, int kp, int kn,
+                                                  int* __restrict__ info) {
+    constexpr int RW = kGP / 64;  // panel rows per lane: 64 RW >= N
+    double* B = base + (size_t)blockIdx.y * stride;
+    int* step_of = w.piv + (size_t)blockIdx.y * 2 * N;
     int* rowpiv = step_of + N;
-    __shared__ int rp_s[kPWG];
+    auto pnbuf = [&](int k0) {
+        return (((k0 / kPWG) & 1) ? w.z : w.pn) + (size_t)blockIdx.y * N * kPWG;
+    };
+    const int c0 = blockIdx.x * kPWG;
+    const int nc = min(kPWG, N - c0);
+    const bool panel = kn >= 0 && c0 == kn;
+    if (kp < 0 && !panel) return;
+    __shared__ double Zs[kPWG][kPWG];
+    __shared__ double strip[kGP][kPWG + 1];
     const int t = threadIdx.x;
-    const int kb = min(kPWG, N - k0);
+    const int r = t;  // this thread's row
+    double v[kPWG];
+#pragma unroll
+    for (int u = 0; u < kPWG; ++u) v[u] = (r < N && u < nc) ? B[(size_t)r * N + c0 + u] : 0.0;
+    if (kp >= 0) {
+        const int kb = min(kPWG, N - kp);
+        const double* pk = pnbuf(kp);
+        {
+            const int tt = t / kPWG, u = t % kPWG;
+            Zs[tt][u] = (tt < kb && u < nc) ? B[(size_t)rowpiv[kp + tt] * N + c0 + u] : 0.0;
+        }
+        __syncthreads();
+        if (r < N) {
+            if (c0 == kp) {
+#pragma unroll
+                for (int u = 0; u < kPWG; ++u) v[u] = (u < nc) ? pk[(size_t)r * kPWG + u] : 0.0;
+            } else {
+                const int st = step_of[r] - kp;
+                const bool isp = st >= 0 && st < kb;
+                double pr[kPWG];
+#pragma unroll
+                for (int tt = 0; tt < kPWG; ++tt) pr[tt] = (tt < kb) ? pk[(size_t)r * kPWG + tt] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kPWG; ++u) v[u] = isp ? 0.0 : v[u];
+#pragma unroll
+                for (int tt = 0; tt < kPWG; ++tt)
+#pragma unroll
+                    for (int u = 0; u < kPWG; ++u) v[u] = fma(pr[tt], Zs[tt][u], v[u]);
+            }
+            if (!panel) {
+#pragma unroll
+                for (int u = 0; u < kPWG; ++u)
+                    if (u < nc) B[(size_t)r * N + c0 + u] = v[u];
+            }
+        }
+    }
+    if (!panel) return;
+    if (kp < 0)
+        for (int q = t; q < N; q += kGP) step_of[q] = -1;
+#pragma unroll
+    for (int u = 0; u < kPWG; ++u) strip[t][u] = (r < N) ? v[u] : 0.0;
+    __syncthreads();
     if (__builtin_amdgcn_readfirstlane(t) < 64) {
         const int lane = t;
+        const int kb = min(kPWG, N - kn);
         double pv[RW][kPWG];
         int tag[RW];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int r = lane + 64 * i;
-            const bool valid = r < N;
-            const int st = valid ? ((k0 > 0) ? step_of[r] : -1) : N;
-            tag[i] = (valid && st < 0) ? 511 - r : -1;
+            const int rr = lane + 64 * i;
+            tag[i] = (rr < N && step_of[rr] < 0) ? 511 - rr : -1;
 #pragma unroll
-            for (int u = 0; u < kPWG; ++u)
-                pv[i][u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
+            for (int u = 0; u < kPWG; ++u) pv[i][u] = strip[rr][u];
         }
         int zeros = 0, rps = 0;
         if (kb == kPWG)
             gj_panel_steps<RW, kPWG, 9, true>(kb, lane, pv, tag, rps, zeros);
         else
             gj_panel_steps<RW, kPWG, 9, false>(kb, lane, pv, tag, rps, zeros);
+        double* pn = pnbuf(kn);
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int r = lane + 64 * i;
-            if (r < N) {
+            const int rr = lane + 64 * i;
+            if (rr < N)
 #pragma unroll
-                for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[i][u];
-                if (k0 == 0) step_of[r] = -1;
-            }
+                for (int u = 0; u < kPWG; ++u) pn[(size_t)rr * kPWG + u] = pv[i][u];
         }
-        // the -1 marks above reach memory before this panel's steps are written
-        __threadfence();
         if (lane < kb) {
-            rowpiv[k0 + lane] = rps;
-            step_of[rps] = k0 + lane;
-            rp_s[lane] = rps;
+            rowpiv[kn + lane] = rps;
+            step_of[rps] = kn + lane;
         }
-        if (lane == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
-    }
-    __syncthreads();
-    for (int e = t; e < kb * N; e += kGP) {
-        const int tt = e / N, j = e - tt * N;
-        z[(size_t)tt * N + j] = B[(size_t)rp_s[tt] * N + j];
+        if (lane == 0 && info) info[blockIdx.y] = (kn == 0 ? 0 : info[blockIdx.y]) + zeros;
     }
 }
 
@@ -846,15 +889,22 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
         w.pn = work;
         w.z = work + (size_t)nblocks * N * kPWG;
         w.piv = reinterpret_cast<int*>(work + (size_t)nblocks * 2 * kPWG * N);
-        const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
-        for (int k0 = 0; k0 < N; k0 += kPWG) {
-            if (N <= 256)
-                k_gjp_panel1<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
-            else if (N <= 2 * kGP)
-                k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
-            else
-                k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
-            k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);
+        if (N <= kGP) {
+            const int npan = (N + kPWG - 1) / kPWG;
+            for (int k = -1; k < npan; ++k) {
+                const int kp = (k >= 0) ? k * kPWG : -1;
+                const int kn = (k + 1 < npan) ? (k + 1) * kPWG : -1;
+                k_gjs_step<<<dim3(npan, nblocks), kGP, 0, s>>>(N, base, stride, w, kp, kn, info);
+            }
+        } else {
+            const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
+            for (int k0 = 0; k0 < N; k0 += kPWG) {
+                if (N <= 2 * kGP)
+                    k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                else
+                    k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);
+            }
         }
         const unsigned ge = (unsigned)std::min<size_t>((NN + 255) / 256, 2048);
         k_gjp_scatter<<<dim3(ge, nblocks), 256, 0, s>>>(N, base, stride, tmp, NN, w);

@@ -162,8 +162,8 @@ def test_preconditioner_graph_replays_match_the_dense_solve():
 def test_preconditioner_wide_blocks_match_dense_solve(N, M):
     """Every diagonal-block inversion variant against the oracle's dense P: the
     register-tile kernel with 1, 2 and 3 panel rows per lane (13- and 14-row tiles on
-    either side of N = 182), and beyond N = 192 the panel and update launches (one
-    wavefront's panel up to N = 256, then 2 and 4 panel rows per thread)."""
+    either side of N = 182), the column-strip launches up to N = 256, and beyond that
+    the panel and update launches with 2 and 4 panel rows per thread."""
     p = api.Problem(N, M, -10.0, 8.0, 3.0, F=0.75, eps=0.1)
     op = oprob(p)
     b = np.random.default_rng(N).standard_normal(p.n_unknowns)

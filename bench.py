@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--q", type=int, default=4, help="preconditioner block half-bandwidth")
+    ap.add_argument("--q", type=int, default=5,
+                    help="preconditioner block half-bandwidth (serving: < 0 chooses by mesh)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--serving", action="store_true",
@@ -175,7 +176,7 @@ def main():
              "precond_build_s": infos[-1].time_precond_s,
              "pair_kernel_share_of_step": kms * 1e-3 / dt}
     if not args.no_extra:
-        extra.update(extra_measurements(api, inputs, cfg, one_solve))
+        extra.update(extra_measurements(api, inputs, cfg, one_solve, args.q))
     out = {
         "metric": "JFNK solves/s & pair-interactions/s (frac FP64 peak); p50/p99 solve latency",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -194,7 +195,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extra_measurements(api, inputs, cfg, one_solve):
+def extra_measurements(api, inputs, cfg, one_solve, q):
     import torch
     res = {}
     p = api.Problem(**cfg)
@@ -220,7 +221,7 @@ def extra_measurements(api, inputs, cfg, one_solve):
         res[f"batch16_{prec}_residuals_per_s"] = 1e3 / ms
     res["paper_table1_181x61_gpu_eval_s"] = PAPER_TABLE1_181x61_GPU_S
     # solve with a prebuilt preconditioner (reused across solves of one mesh and F)
-    P = api.Preconditioner(p, 4)
+    P = api.Preconditioner(p, q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, info = one_solve(precond=P)
@@ -290,7 +291,7 @@ def serving(args):
     servers = {}
     for prec in ("fp32", "fp64"):
         servers[prec] = api.Server(hbm_budget_bytes=64e9, max_slots=32, precision=prec,
-                                   fallback_fp64=True, q_blocks=args.q)
+                                   fallback_fp64=True, q_blocks=-1)
         out[f"closed_loop_{prec}"] = run(servers[prec], base)   # warms the caches
     capacity = out["closed_loop_fp32"]["solves_per_s"]
     rate = 0.8 * capacity
@@ -305,7 +306,7 @@ def serving(args):
             "config": {"workload": (f"serving: {args.requests} requests, Poisson arrivals at "
                                     f"{rate:.2f}/s (80% of closed-loop mixed capacity), meshes "
                                     f"61x21/121x41/181x61/241x81, F~U[0.5,1], eps~U[0.05,0.4], "
-                                    f"seed 0, q={args.q}")},
+                                    f"seed 0, q by mesh (5 for N <= 200, 8 beyond)")},
             "p50_latency_s": out["poisson_fp32"]["p50_latency_s"],
             "p99_latency_s": out["poisson_fp32"]["p99_latency_s"],
             "arrival_rate_per_s": rate, "runs": out}

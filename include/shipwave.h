@@ -140,7 +140,7 @@ typedef struct {
     int32_t max_newton;    /* default 50 */
     int32_t gmres_restart; /* Krylov dimension m before restart (default 30) */
     int32_t max_gmres;     /* GMRES iterations per Newton step (default 200) */
-    int32_t q_blocks;      /* preconditioner block half-bandwidth (default 4; <0 -> 1) */
+    int32_t q_blocks;      /* preconditioner block half-bandwidth (default 5; <0 -> 1) */
     int32_t precision;     /* SW_PREC_FP64, or SW_PREC_FP32: FP32-Kahan inner JVPs, FP64 outer */
     int32_t weights;       /* SW_WEIGHTS_* */
     int32_t spline_bc;     /* SW_SPLINE_* */
@@ -196,7 +196,8 @@ typedef struct {
     int32_t max_slots;        /* solves advanced together */
     int32_t fallback_fp64;    /* 1: a mixed-precision solve that fails is retried in FP64 */
     double tol;               /* Newton tolerance (default 1e-10) */
-    int32_t q_blocks;         /* preconditioner half-bandwidth (default 1) */
+    int32_t q_blocks;         /* preconditioner half-bandwidth; < 0: by mesh, 5 for N <= 200,
+                                 8 beyond */
     int32_t precision;        /* SW_PREC_* of the inner JVPs */
 } sw_server_opts;
 typedef struct {

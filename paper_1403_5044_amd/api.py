@@ -237,11 +237,14 @@ class Result:
 
 
 class Server:
-    """Continuous-batching solve server (one worker thread and stream on the GPU)."""
+    """Continuous-batching solve server (one worker thread and stream on the GPU).
+
+    q_blocks < 0 lets the server choose the preconditioner band by mesh (5 for N <= 200,
+    8 beyond)."""
 
     def __init__(self, hbm_budget_bytes: float = 8e9, max_slots: int = 16,
                  precision: str = "fp32", fallback_fp64: bool = True, tol: float = 1e-10,
-                 q_blocks: int = 4):
+                 q_blocks: int = -1):
         self.lib = _lib()
         o = L.SwServerOpts()
         o.hbm_budget_bytes = float(hbm_budget_bytes)

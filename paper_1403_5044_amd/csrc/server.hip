@@ -32,6 +32,11 @@
 #include "solve_task.hpp"
 
 namespace sw {
+
+// Preconditioner half-bandwidth chosen by mesh when the caller leaves it to the server:
+// the wider band pays for its set-up on the larger meshes (measured on the serving mix).
+int mesh_q(const Geo& g) { return g.N <= 200 ? 5 : 8; }
+
 namespace {
 
 double clock_s(std::chrono::steady_clock::time_point t0) {
@@ -104,9 +109,9 @@ struct sw_server {
     void retire(Active& a, int status);
     const sw_precond* get_precond(const Geo& g, size_t& charged);
     void release_precond(const Geo& g);
+    int q_of(const Geo& g) const { return opts.q_blocks >= 0 ? opts.q_blocks : mesh_q(g); }
     std::tuple<int, int, double, double, double, long, int> pkey(const Geo& g) const {
-        return std::make_tuple(g.N, g.M, g.x1, g.xN, g.yM, std::lround(g.F / kFBucket),
-                               opts.q_blocks);
+        return std::make_tuple(g.N, g.M, g.x1, g.xN, g.yM, std::lround(g.F / kFBucket), q_of(g));
     }
 };
 
@@ -121,7 +126,7 @@ const sw_precond* sw_server::get_precond(const Geo& g, size_t& charged) {
     }
     Geo gr = g;
     gr.F = std::lround(g.F / kFBucket) * kFBucket;
-    sw_precond* P = precond_build(gr, opts.q_blocks, stream);
+    sw_precond* P = precond_build(gr, q_of(g), stream);
     charged = precond_bytes(P);
     pcache[key] = CachedP{P, charged, 1, ++use_clock};
     return P;
@@ -184,7 +189,7 @@ bool sw_server::admit_one(std::unique_lock<std::mutex>& lk) {
     }
     const size_t task_bytes = task_bytes_of(g);
     const bool cached = pcache.count(pkey(g)) > 0;
-    const size_t p_bytes = cached ? 0 : precond_bytes_estimate(g, opts.q_blocks);
+    const size_t p_bytes = cached ? 0 : precond_bytes_estimate(g, q_of(g));
     const double budget = opts.hbm_budget_bytes;
     if ((double)(task_bytes + p_bytes) > budget) {
         queue.pop_front();
@@ -367,7 +372,6 @@ int32_t shipwave_server_create(const sw_server_opts* opts, sw_server** out) {
         auto* s = new sw_server();
         s->opts = *opts;
         if (!(s->opts.tol > 0.0)) s->opts.tol = 1e-10;
-        if (s->opts.q_blocks < 0) s->opts.q_blocks = 4;
         s->t0 = std::chrono::steady_clock::now();
         if (hipGetDevice(&s->device) != hipSuccess ||
             hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -385,7 +389,7 @@ int32_t shipwave_server_request_bytes(const sw_server_opts* opts, const sw_reque
     return guard([&]() -> int32_t {
         SW_REQUIRE(opts && req && bytes, "null pointer");
         const Geo g = request_geo(*req);
-        const int q = opts->q_blocks < 0 ? 4 : opts->q_blocks;
+        const int q = opts->q_blocks >= 0 ? opts->q_blocks : mesh_q(g);
         *bytes = (uint64_t)(task_bytes_of(g) + precond_bytes_estimate(g, q));
         return SW_OK;
     });

@@ -432,7 +432,7 @@ void shipwave_solve_opts_default(sw_solve_opts* o) {
     o->max_newton = 50;
     o->gmres_restart = 30;
     o->max_gmres = 200;
-    o->q_blocks = 4;
+    o->q_blocks = 5;
     o->precision = SW_PREC_FP64;
     o->weights = SW_WEIGHTS_TRAPEZOID;
     o->spline_bc = SW_SPLINE_CLAMPED0;

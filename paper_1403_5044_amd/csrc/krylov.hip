@@ -162,6 +162,91 @@ __global__ __launch_bounds__(kThreads) void k_quot(int n, const double* __restri
         out[t] = (Ep[t] - Eu[t]) * r;
 }
 
+// Fused forms for the Krylov step; each finishes a two-pass reduction in the same order
+// as k_norm2 / k_dots2, so their results are bitwise those of the separate launches.
+
+// Final pass of norm_inf_2 on z (partials in work), the JVP step from it (as k_jvp_h),
+// and out = u + step z.  Workgroup 0 stores the norms of z and h = [step, 1/step].
+__global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B, const double* __restrict__ work,
+                                                         const double* __restrict__ norms_u,
+                                                         double sqrt_eps, double sqrt_n,
+                                                         double* __restrict__ norms_z,
+                                                         double* __restrict__ h,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ z,
+                                                         double* __restrict__ out) {
+    __shared__ double st_s;
+    if (threadIdx.x == 0) {
+        double m = 0.0, s = 0.0;
+        for (int b = 0; b < B; ++b) {
+            m = fmax(m, work[b]);
+            s += work[B + b];
+        }
+        const double nz = sqrt(s);
+        double st = 0.0, inv = 0.0;
+        if (nz > 0.0) {
+            st = sqrt_eps * (sqrt_n + norms_u[1]) / nz;
+            inv = 1.0 / st;
+        }
+        st_s = st;
+        if (blockIdx.x == 0) {
+            norms_z[0] = (s == s && s <= 1.7976931348623157e308) ? m : s;
+            norms_z[1] = nz;
+            h[0] = st;
+            h[1] = inv;
+        }
+    }
+    __syncthreads();
+    const double st = st_s;
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+        out[t] = fma(st, z[t], u[t]);
+}
+
+// w = (Ep - Eu) / step (as k_quot; stored by the blocks of V_0) and the partial dots of
+// V_i with it (as k_dots1).
+__global__ __launch_bounds__(kThreads) void k_dots1_quot(int n, const double* __restrict__ V,
+                                                         size_t ldv, const double* __restrict__ Ep,
+                                                         const double* __restrict__ Eu,
+                                                         const double* __restrict__ h,
+                                                         double* __restrict__ w,
+                                                         double* __restrict__ work) {
+    __shared__ double sh[kThreads / 64];
+    const int i = blockIdx.y;
+    const double* v = V + (size_t)i * ldv;
+    const double r = h[1];
+    double s = 0.0;
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+        const double wt = (Ep[t] - Eu[t]) * r;
+        if (i == 0) w[t] = wt;
+        s = fma(v[t], wt, s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) work[(size_t)i * gridDim.x + blockIdx.x] = s;
+}
+
+// Final pass of dots (partials in work, B per vector) in every block, then
+// w -= sum_i h[i] V_i (as k_gemv_sub).  Block 0 stores h.
+__global__ __launch_bounds__(kThreads) void k_gemv_sub_dots(int n, int k, int B,
+                                                            const double* __restrict__ V,
+                                                            size_t ldv,
+                                                            const double* __restrict__ work,
+                                                            double* __restrict__ hout,
+                                                            double* __restrict__ w) {
+    extern __shared__ double hs[];
+    for (int i = threadIdx.x; i < k; i += kThreads) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += work[(size_t)i * B + b];
+        hs[i] = s;
+        if (blockIdx.x == 0) hout[i] = s;
+    }
+    __syncthreads();
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+        double s = w[t];
+        for (int i = 0; i < k; ++i) s = fma(-hs[i], V[(size_t)i * ldv + t], s);
+        w[t] = s;
+    }
+}
+
 __global__ void k_flat(int NM, double* u) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * NM; t += gridDim.x * blockDim.x)
         u[t] = (t < NM) ? 1.0 : 0.0;
@@ -226,5 +311,35 @@ void quotient(int n, const double* Ep, const double* Eu, const double* h, double
 }
 
 void flat_state(int NM, double* u, hipStream_t s) { k_flat<<<256, 256, 0, s>>>(NM, u); }
+
+void shift_auto(int n, const double* u, const double* z, const double* norms_u, double sqrt_eps,
+                double sqrt_n, double* norms_z, double* h, double* out, double* work,
+                hipStream_t s) {
+    const int B = red_blocks(n);
+    k_norm1<<<B, kThreads, 0, s>>>(n, z, work);
+    k_shift_auto<<<ew_blocks(n), kThreads, 0, s>>>(n, B, work, norms_u, sqrt_eps, sqrt_n, norms_z,
+                                                    h, u, z, out);
+}
+
+// Every block of the subtraction re-reads the k B partials; beyond this many the separate
+// final-pass launch is cheaper.
+constexpr int kFusedPartials = 2048;
+
+void cgs_pass(int n, int k, const double* V, size_t ldv, const double* w_in_Ep,
+              const double* Eu, const double* h, double* w, double* hout, double* work,
+              hipStream_t s) {
+    const int B = red_blocks(n);
+    if (w_in_Ep)
+        k_dots1_quot<<<dim3(B, k), kThreads, 0, s>>>(n, V, ldv, w_in_Ep, Eu, h, w, work);
+    else
+        k_dots1<<<dim3(B, k), kThreads, 0, s>>>(n, V, ldv, w, work);
+    if ((size_t)k * B <= (size_t)kFusedPartials) {
+        k_gemv_sub_dots<<<ew_blocks(n), kThreads, (size_t)k * sizeof(double), s>>>(
+            n, k, B, V, ldv, work, hout, w);
+    } else {
+        k_dots2<<<(k + 63) / 64, 64, 0, s>>>(k, B, work, hout);
+        k_gemv_sub<<<ew_blocks(n), kThreads, 0, s>>>(n, k, V, ldv, hout, w);
+    }
+}
 
 }  // namespace sw

@@ -128,18 +128,16 @@ void SolveTask::pre(hipStream_t s) {
                 scale_copy(n_, 1.0 / pending_scale_, vj, vj, s);
             }
             precond_apply(P_, vj, z_, s);
-            norm_inf_2(n_, z_, hd_ + 2 * m + 6, red_, s);
-            jvp_step(hd_ + 2 * m + 4, hd_ + 2 * m + 6, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 8, s);
-            shift(n_, u_, z_, hd_ + 2 * m + 8, xs_, s);
+            shift_auto(n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
+                       hd_ + 2 * m + 8, xs_, red_, s);
             req_x = xs_;
             req_E = Ejv_;
             req_g = &gin_;
             break;
         }
         case Phase::Restart:
-            norm_inf_2(n_, du_, hd_ + 2 * m + 6, red_, s);
-            jvp_step(hd_ + 2 * m + 4, hd_ + 2 * m + 6, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 8, s);
-            shift(n_, u_, du_, hd_ + 2 * m + 8, xs_, s);
+            shift_auto(n_, u_, du_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
+                       hd_ + 2 * m + 8, xs_, red_, s);
             req_x = xs_;
             req_E = Ejv_;
             req_g = &gin_;
@@ -171,11 +169,9 @@ void SolveTask::post(hipStream_t s) {
             break;
         case Phase::Krylov: {
             double* vn = V_ + (size_t)(j_ + 1) * n_;
-            quotient(n_, Ejv_, Ein_, hd_ + 2 * m + 8, vn, s);
-            dots(n_, j_ + 1, V_, n_, vn, hd_, red_, s);
-            gemv_sub(n_, j_ + 1, V_, n_, hd_, vn, s);
-            dots(n_, j_ + 1, V_, n_, vn, hd_ + (m + 1), red_, s);
-            gemv_sub(n_, j_ + 1, V_, n_, hd_ + (m + 1), vn, s);
+            // vn = J z by the difference quotient, then two Gram-Schmidt passes
+            cgs_pass(n_, j_ + 1, V_, n_, Ejv_, Ein_, hd_ + 2 * m + 8, vn, hd_, red_, s);
+            cgs_pass(n_, j_ + 1, V_, n_, nullptr, nullptr, nullptr, vn, hd_ + (m + 1), red_, s);
             norm_inf_2(n_, vn, hd_ + 2 * m + 2, red_, s);
             SW_HIP(hipMemcpyAsync(pin_out_, hd_, (2 * m + 4) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));

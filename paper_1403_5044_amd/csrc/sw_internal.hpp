@@ -145,6 +145,17 @@ void shift(int n, const double* u, const double* z, const double* h, double* out
 void quotient(int n, const double* Ep, const double* Eu, const double* h, double* out,
               hipStream_t s);
 void flat_state(int NM, double* u, hipStream_t s);  // phi_x = 1, zeta_x = 0
+// norm_inf_2(z) into norms_z, jvp_step(norms_u, norms_z) into h and shift(u, z, h) into
+// out, in two launches (work as for norm_inf_2).
+void shift_auto(int n, const double* u, const double* z, const double* norms_u, double sqrt_eps,
+                double sqrt_n, double* norms_z, double* h, double* out, double* work,
+                hipStream_t s);
+// One classical Gram-Schmidt pass against V_0..V_{k-1}: hout = V^T w, w -= V hout.  With
+// Ep != nullptr, w is first set to (Ep - Eu) / h[0] (quotient()).  Two launches while
+// the reduction partials are few, three otherwise; the results equal those of
+// quotient(), dots() and gemv_sub().
+void cgs_pass(int n, int k, const double* V, size_t ldv, const double* Ep, const double* Eu,
+              const double* h, double* w, double* hout, double* work, hipStream_t s);
 void residual_one(const Geo& g, const double* u, double* E, hipStream_t s);
 // work doubles for dots() with up to k vectors and for norm_inf_2()
 size_t reduce_work_doubles(int n, int k);

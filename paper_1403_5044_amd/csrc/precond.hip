@@ -12,13 +12,14 @@
 //   block, the same for every row l).
 //
 // S is factorised by block LU without pivoting between blocks (partial
-// pivoting inside each N x N diagonal block, by Gauss-Jordan).  Stored per
-// block row l (2q+1 slots of N x N):
-//   slot q:        Dinv_l   = (updated diagonal block)^{-1}
-//   slot q-d (d>0): L_{l,l-d} = S~_{l,l-d} Dinv_{l-d}
-//   slot q+d (d>0): G_{l,l+d} = Dinv_l U_{l,l+d}
-// so that  forward  y_l = t_l - sum_d L_{l,l-d} y_{l-d}
-//          backward x_l = Dinv_l y_l - sum_d G_{l,l+d} x_{l+d}
+// pivoting inside each N x N diagonal block, by Gauss-Jordan), eliminating the
+// block rows in an order that starts at both ends of the band (make_order).
+// Stored per block row l (2q+1 slots of N x N; slot q + c - l holds column c):
+//   slot q:                       Dinv_l    = (updated diagonal block)^{-1}
+//   column c eliminated before l: L_{l,c} = S~_{l,c} Dinv_c
+//   column c eliminated after l:  G_{l,c} = Dinv_l S~_{l,c}
+// so that, in elimination order,  forward  y_l = t_l - sum L_{l,c} y_c
+//                  and in reverse, backward x_l = Dinv_l y_l - sum G_{l,c} x_c
 // are block GEMVs.  q = 0 (block bandwidth 1) makes every block independent.
 #include "sw_internal.hpp"
 #include "sw_device.hpp"
@@ -37,6 +38,7 @@ constexpr int kMaxSuperTerms = 184;
 struct SuperStep {
     int nrow;
     int first[kMaxSuperRows + 1];
+    double* out[kMaxSuperRows];  // output block (N doubles) of each row
     const double* blk[kMaxSuperTerms];
     const double* vec[kMaxSuperTerms];
 };
@@ -53,14 +55,14 @@ struct sw_precond {
     double* work = nullptr;  // [4][NM]
     double* tmp = nullptr;   // workspace of the diagonal-block inversion
     double* tmp2 = nullptr;  // [2q][N][N] products of one factorisation step
-    int* info = nullptr;     // [M] zero pivots seen
+    int* info = nullptr;     // [2M] zero pivots seen, two per factorisation step
     void* terms = nullptr;   // device GemvTerm lists of the band substitution steps
     hipGraphExec_t subst = nullptr;  // the substitution launches, captured once
     std::vector<int> fwd_off, fwd_cnt, bwd_off, bwd_cnt;
     int sb = 0;                      // block rows per super row (0: one block row per step)
     double* W = nullptr;             // super-row operators (nonzero N x N blocks)
     std::vector<sw::SuperStep> fsteps, bsteps;  // kernel arguments of the super-row steps
-    std::vector<int> sl0;                       // first block row of each super row
+    std::vector<int> ord;                       // elimination order of the block rows
     size_t bytes = 0;
     int device = -1;
 };
@@ -1226,8 +1228,7 @@ __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const doub
 // One workgroup per output row of a super-row step (SuperStep): its four wavefronts
 // take every fourth term, so that each has few dependent load rounds, and the four
 // partial dot products are added in a fixed order.
-__global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st,
-                                                    double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st) {
     const int row = blockIdx.x;
     const int i = row / N, r = row - i * N;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1254,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st,
     __shared__ double part[4];
     if (lane == 0) part[w] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) out[row] = (part[0] + part[1]) + (part[2] + part[3]);
+    if (threadIdx.x == 0) st.out[i][r] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // dst = 0, I, src or -src for a batch of N x N blocks; grid (chunks, jobs)
@@ -1311,16 +1312,18 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
 }  // namespace
 
 namespace {
-// scratch blocks: the inversion's output block (N > 192) and two halves of 2q products
-// (factorisation steps of either parity), or M inverses at once (q = 0, N > 192)
+// scratch blocks: the output blocks of two inversions at once (N > 192) and, per chain of
+// the elimination, 2q products for steps of either parity; or M inverses at once (q = 0,
+// N > 192)
 size_t tmp2_blocks(const Geo& g, int q) {
-    return (size_t)std::max({4 * q + 1, 1, (q == 0 && g.N > 192) ? g.M : 1});
+    if (q == 0) return (size_t)(g.N > 192 ? g.M : 1);
+    return (size_t)(8 * q + 2);
 }
 
-// workspace of the diagonal-block inversion (N > 192), at least one N x N block
+// workspace of the diagonal-block inversions (N > 192), at least one N x N block
 size_t gj_work_size(const Geo& g, int q) {
     const size_t NN = (size_t)g.N * g.N;
-    return std::max(NN, gj_work_doubles(g.N, q == 0 ? g.M : 1));
+    return std::max(NN, gj_work_doubles(g.N, q == 0 ? g.M : 2));
 }
 
 int k3_chunks(const Geo& g) {
@@ -1329,15 +1332,40 @@ int k3_chunks(const Geo& g) {
 }
 }  // namespace
 
+// ---- elimination order ----------------------------------------------------------------
+// The band is eliminated from both ends: the top rows [0, k) downwards and the bottom
+// rows [k+q, M) upwards form two chains that share no block (a separator of q rows keeps
+// them more than q apart), so their steps run side by side in the same launches.  The
+// separator rows [k, k+q) go last.  Position p of the order eliminates block row ord[p];
+// the factors are those of block LU of the band with rows and columns in that order.
+struct Order {
+    int k = 0, nB = 0;
+    std::vector<int> ord, rank;  // position -> block row, block row -> position
+};
+
+Order make_order(int M, int q) {
+    Order o;
+    o.k = (M - q + 1) / 2;
+    o.nB = M - q - o.k;
+    for (int l = 0; l < o.k; ++l) o.ord.push_back(l);
+    for (int l = M - 1; l >= o.k + q; --l) o.ord.push_back(l);
+    for (int l = o.k; l < o.k + q; ++l) o.ord.push_back(l);
+    o.rank.assign(M, 0);
+    for (int p = 0; p < M; ++p) o.rank[o.ord[p]] = p;
+    return o;
+}
+
 // ---- super-row substitution -----------------------------------------------------------
-// The block substitutions are regrouped into super rows of b block rows.  Forward
-// (L unit block-lower with band q): the blocks y_L of one super row satisfy
-//     A_L y_L = t_L - C_L y_prev,   A_L = I + (L inside the super row),
-// so y_L = W_L [y_prev; t_L] with W_L = A_L^{-1} [-C_L | I].  Backward (x_l = Dinv_l y_l
-// - sum_d G_{l,l+d} x_{l+d}): x_L = W'_L [y_L; x_next], W'_L = B_L^{-1} [Dg_L | -C'_L],
-// B_L = I + (G inside the super row).  W and W' are formed once by block substitution
-// on their right-hand sides (GEMMs), keeping only the nonzero blocks, and each
-// application then takes 2 ceil(M/b) launches instead of 2M.
+// The block substitutions are regrouped into super rows: runs of b consecutive positions
+// of the elimination order inside one of its three segments.  Forward (L unit lower in
+// that order): the blocks y_R of a super row R satisfy
+//     A_R y_R = t_R - C_R y_ext,   A_R = I + (L inside R),
+// with y_ext the earlier rows that R couples to, so y_R = W_R [y_ext; t_R] with
+// W_R = A_R^{-1} [-C_R | I].  Backward (x_r = Dinv_r y_r - sum G_{r,c} x_c over later c):
+// x_R = W'_R [y_R; x_ext], W'_R = B_R^{-1} [Dg_R | -C'_R], B_R = I + (G inside R).  W and
+// W' are formed once by block substitution on their right-hand sides (GEMMs), keeping
+// only the nonzero blocks.  A top and a bottom super row depend on each other in neither
+// sweep, so each pair runs as one launch.
 namespace {
 #ifndef SW_SUPER_TARGET
 #define SW_SUPER_TARGET 1000.0
@@ -1345,75 +1373,135 @@ namespace {
 constexpr double kSuperTarget = SW_SUPER_TARGET;  // b N: super-row height in grid rows
 
 struct SuperRow {
-    int l0 = 0, nb = 0, nprev = 0;   // first block row, block rows, coupled outside blocks
-    std::vector<std::vector<int>> id;  // [nb][nb + nprev]: operator block index or -1
+    std::vector<int> rows;             // block rows in elimination order
+    std::vector<int> ext;              // coupled rows outside R: earlier (fwd) / later (bwd)
+    std::vector<std::vector<int>> id;  // [rows][inputs]: operator block index or -1
+    int terms = 0;
 };
 struct SuperPlan {
     int b = 0;
-    std::vector<SuperRow> fwd, bwd;
+    std::vector<SuperRow> fwd, bwd;          // fwd[i] and bwd[i] cover the same rows
+    std::vector<std::vector<int>> stages;    // super rows launched together, forward order
     size_t nblocks = 0;
 };
 
-int super_rows(const Geo& g, int q) {
-    if (q == 0) return 0;
-    int b = (int)std::lround(kSuperTarget / g.N);
-    b = std::min({b, g.M, kMaxSuperRows});
-    // every block row couples to at most q outside and b inside blocks
-    while (b > 1 && b * (b + q) > kMaxSuperTerms) --b;
-    return b > 1 ? b : 0;
-}
+bool coupled(int r, int c, int q) { return r != c && std::abs(r - c) <= q; }
 
-// Nonzero block pattern of W (forward) and W' (backward).  Forward input blocks are
-// [y_{l0-nprev} .. y_{l0-1}, t_{l0} .. t_{l0+nb-1}]; backward [y_{l0} .. y_{l0+nb-1},
-// x_{l0+nb} .. x_{l0+nb+nprev-1}].
-SuperPlan plan_super(const Geo& g, int q, int b) {
-    SuperPlan P;
-    P.b = b;
-    if (b <= 1) return P;
-    size_t next = 0;
-    for (int l0 = 0; l0 < g.M; l0 += b) {
-        const int nb = std::min(b, g.M - l0);
-        {  // forward
-            SuperRow R;
-            R.l0 = l0;
-            R.nb = nb;
-            R.nprev = std::min(q, l0);
-            const int nin = nb + R.nprev, nq = R.nprev;
-            std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
-            for (int i = 0; i < nb; ++i) {
-                for (int c = 0; c < nq; ++c) nz[i][c] = (i + nq - c >= 1 && i + nq - c <= q);
-                nz[i][nq + i] = 1;
-                for (int d = 1; d <= std::min(q, i); ++d)
-                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[i - d][c];
+// Nonzero block pattern of W (forward) or W' (backward) of the super row with rows R.
+// Forward inputs are [y_ext..., t_R...]; backward [y_R..., x_ext...].
+SuperRow make_super_row(const Order& o, int q, const std::vector<int>& R, bool fwd,
+                        size_t& next) {
+    SuperRow S;
+    S.rows = R;
+    const int nb = (int)R.size();
+    const int p0 = o.rank[R.front()], p1 = o.rank[R.back()];
+    const int M = (int)o.ord.size();
+    for (int c = 0; c < M; ++c) {
+        const int pc = o.rank[c];
+        if (fwd ? pc >= p0 : pc <= p1) continue;
+        for (int r : R)
+            if (coupled(r, c, q)) {
+                S.ext.push_back(c);
+                break;
             }
-            R.id.assign(nb, std::vector<int>(nin, -1));
-            for (int i = 0; i < nb; ++i)
-                for (int c = 0; c < nin; ++c)
-                    if (nz[i][c]) R.id[i][c] = (int)next++;
-            P.fwd.push_back(std::move(R));
+    }
+    const int ne = (int)S.ext.size(), nin = nb + ne;
+    std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
+    if (fwd) {
+        for (int i = 0; i < nb; ++i) {
+            for (int c = 0; c < ne; ++c) nz[i][c] = coupled(R[i], S.ext[c], q);
+            nz[i][ne + i] = 1;
+            for (int j = 0; j < i; ++j)
+                if (coupled(R[i], R[j], q))
+                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[j][c];
         }
-        {  // backward
-            SuperRow R;
-            R.l0 = l0;
-            R.nb = nb;
-            R.nprev = std::min(q, g.M - (l0 + nb));
-            const int nin = nb + R.nprev;
-            std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
-            for (int i = nb - 1; i >= 0; --i) {
-                nz[i][i] = 1;
-                for (int c = nb; c < nin; ++c) nz[i][c] = (c - i >= 1 && c - i <= q);
-                for (int d = 1; d <= std::min(q, nb - 1 - i); ++d)
-                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[i + d][c];
-            }
-            R.id.assign(nb, std::vector<int>(nin, -1));
-            for (int i = 0; i < nb; ++i)
-                for (int c = 0; c < nin; ++c)
-                    if (nz[i][c]) R.id[i][c] = (int)next++;
-            P.bwd.push_back(std::move(R));
+    } else {
+        for (int i = nb - 1; i >= 0; --i) {
+            nz[i][i] = 1;
+            for (int c = 0; c < ne; ++c) nz[i][nb + c] = coupled(R[i], S.ext[c], q);
+            for (int j = i + 1; j < nb; ++j)
+                if (coupled(R[i], R[j], q))
+                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[j][c];
         }
     }
+    S.id.assign(nb, std::vector<int>(nin, -1));
+    for (int i = 0; i < nb; ++i)
+        for (int c = 0; c < nin; ++c)
+            if (nz[i][c]) {
+                S.id[i][c] = (int)next++;
+                ++S.terms;
+            }
+    return S;
+}
+
+// Super rows of b positions per segment (fewer for the separator if its rows do not fit
+// one step); b = 0 if b = 1 would be needed.
+SuperPlan plan_super(const Order& o, int q, int b) {
+    SuperPlan P;
+    if (b <= 1) return P;
+    P.b = b;
+    const int M = (int)o.ord.size();
+    size_t next = 0;
+    auto add = [&](int pa, int pb) {  // positions [pa, pb)
+        std::vector<int> R(o.ord.begin() + pa, o.ord.begin() + pb);
+        P.fwd.push_back(make_super_row(o, q, R, true, next));
+        P.bwd.push_back(make_super_row(o, q, R, false, next));
+        return (int)P.fwd.size() - 1;
+    };
+    std::vector<int> top, bot;
+    for (int p = 0; p < o.k; p += b) top.push_back(add(p, std::min(p + b, o.k)));
+    for (int p = o.k; p < o.k + o.nB; p += b) bot.push_back(add(p, std::min(p + b, o.k + o.nB)));
+    auto fits = [&](const std::vector<int>& st) {
+        int rows = 0, tf = 0, tb = 0;
+        for (int i : st) {
+            rows += (int)P.fwd[i].rows.size();
+            tf += P.fwd[i].terms;
+            tb += P.bwd[i].terms;
+        }
+        return rows <= kMaxSuperRows && std::max(tf, tb) <= kMaxSuperTerms;
+    };
+    for (size_t j = 0; j < std::max(top.size(), bot.size()); ++j) {
+        std::vector<int> st;
+        if (j < top.size()) st.push_back(top[j]);
+        if (j < bot.size()) st.push_back(bot[j]);
+        if (st.size() == 2 && !fits(st)) {
+            P.stages.push_back({st[0]});
+            P.stages.push_back({st[1]});
+        } else {
+            P.stages.push_back(st);
+        }
+    }
+    for (int p = o.k + o.nB; p < M;) {
+        int e = std::min(p + b, M);
+        const size_t mark = next;
+        int i = add(p, e);
+        while (!fits({i}) && e - p > 1) {  // shrink the separator's super row
+            P.fwd.pop_back();
+            P.bwd.pop_back();
+            next = mark;
+            --e;
+            i = add(p, e);
+        }
+        P.stages.push_back({i});
+        p = e;
+    }
+    for (const auto& st : P.stages)
+        if (!fits(st)) return SuperPlan{};
     P.nblocks = next;
     return P;
+}
+
+// Super-row height: b N near kSuperTarget grid rows, lowered until every step fits the
+// kernel's argument block; 0 (one block row per step) if no b > 1 fits.
+SuperPlan choose_super(const Geo& g, const Order& o, int q) {
+    if (q == 0) return SuperPlan{};
+    int b = (int)std::lround(kSuperTarget / g.N);
+    b = std::min({b, g.M, kMaxSuperRows});
+    for (; b > 1; --b) {
+        SuperPlan P = plan_super(o, q, b);
+        if (P.b > 1) return P;
+    }
+    return SuperPlan{};
 }
 
 void fill_batched(int N, const std::vector<FillJob>& jobs, hipStream_t s) {
@@ -1433,106 +1521,182 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
     const int q = P->q, N = g.N;
     const size_t NN = (size_t)N * N, NM = g.NM;
     auto Wb = [&](int id) { return P->W + (size_t)id * NN; };
-    auto Sb = [&](int l, int slot) { return P->S + blk_off(P, l, slot); };
+    auto Sb = [&](int r, int c) { return P->S + blk_off(P, r, c - r + q); };
     std::vector<FillJob> fills;
     for (const SuperRow& R : plan.fwd) {
-        const int nq = R.nprev;
-        for (int i = 0; i < R.nb; ++i)
-            for (int c = 0; c < R.nb + nq; ++c) {
+        const int nb = (int)R.rows.size(), ne = (int)R.ext.size();
+        for (int i = 0; i < nb; ++i)
+            for (int c = 0; c < nb + ne; ++c) {
                 if (R.id[i][c] < 0) continue;
                 FillJob j{Wb(R.id[i][c]), nullptr, 0, 0};
-                if (c < nq && i + nq - c >= 1 && i + nq - c <= q) {
-                    j.src = Sb(R.l0 + i, q - (i + nq - c));  // L_{l, l-d}, d = i + nq - c
+                if (c < ne && coupled(R.rows[i], R.ext[c], q)) {
+                    j.src = Sb(R.rows[i], R.ext[c]);  // L_{r,c}
                     j.mode = 3;
-                } else if (c == nq + i) {
+                } else if (c == ne + i) {
                     j.mode = 1;
                 }
                 fills.push_back(j);
             }
     }
     for (const SuperRow& R : plan.bwd) {
-        for (int i = 0; i < R.nb; ++i)
-            for (int c = 0; c < R.nb + R.nprev; ++c) {
+        const int nb = (int)R.rows.size(), ne = (int)R.ext.size();
+        for (int i = 0; i < nb; ++i)
+            for (int c = 0; c < nb + ne; ++c) {
                 if (R.id[i][c] < 0) continue;
                 FillJob j{Wb(R.id[i][c]), nullptr, 0, 0};
                 if (c == i) {
-                    j.src = Sb(R.l0 + i, q);  // Dinv_l
+                    j.src = Sb(R.rows[i], R.rows[i]);  // Dinv_r
                     j.mode = 2;
-                } else if (c >= R.nb && c - i >= 1 && c - i <= q) {
-                    j.src = Sb(R.l0 + i, q + (c - i));  // G_{l, l+d}, d = c - i
+                } else if (c >= nb && coupled(R.rows[i], R.ext[c - nb], q)) {
+                    j.src = Sb(R.rows[i], R.ext[c - nb]);  // G_{r,c}
                     j.mode = 3;
                 }
                 fills.push_back(j);
             }
     }
     fill_batched(N, fills, s);
-    // forward levels: W_i -= L_{l0+i, l0+i-d} W_{i-d}
+    // forward levels: W_i -= L_{R_i, R_{i-d}} W_{i-d}
     for (int i = 1; i < plan.b; ++i)
         for (int d = 1; d <= std::min(q, i); ++d) {
             std::vector<GemmJob> jobs;
             for (const SuperRow& R : plan.fwd) {
-                if (i >= R.nb) continue;
-                for (int c = 0; c < R.nb + R.nprev; ++c) {
+                if (i >= (int)R.rows.size() || !coupled(R.rows[i], R.rows[i - d], q)) continue;
+                for (size_t c = 0; c < R.id[i].size(); ++c) {
                     const int src = R.id[i - d][c];
                     if (src < 0) continue;
                     double* dst = Wb(R.id[i][c]);
-                    jobs.push_back(GemmJob{Sb(R.l0 + i, q - d), Wb(src), dst, dst});
+                    jobs.push_back(GemmJob{Sb(R.rows[i], R.rows[i - d]), Wb(src), dst, dst});
                 }
             }
             gemm_batched(N, -1.0, jobs, s);
         }
-    // backward levels (e = nb - 1 - i): W'_i -= G_{l0+i, l0+i+d} W'_{i+d}
+    // backward levels (i = nb - 1 - e): W'_i -= G_{R_i, R_{i+d}} W'_{i+d}
     for (int e = 1; e < plan.b; ++e)
         for (int d = 1; d <= std::min(q, e); ++d) {
             std::vector<GemmJob> jobs;
             for (const SuperRow& R : plan.bwd) {
-                const int i = R.nb - 1 - e;
-                if (i < 0) continue;
-                for (int c = 0; c < R.nb + R.nprev; ++c) {
+                const int i = (int)R.rows.size() - 1 - e;
+                if (i < 0 || !coupled(R.rows[i], R.rows[i + d], q)) continue;
+                for (size_t c = 0; c < R.id[i].size(); ++c) {
                     const int src = R.id[i + d][c];
                     if (src < 0) continue;
                     double* dst = Wb(R.id[i][c]);
-                    jobs.push_back(GemmJob{Sb(R.l0 + i, q + d), Wb(src), dst, dst});
+                    jobs.push_back(GemmJob{Sb(R.rows[i], R.rows[i + d]), Wb(src), dst, dst});
                 }
             }
             gemm_batched(N, -1.0, jobs, s);
         }
-    // step arguments: forward inputs y (= work + 3 NM) and t2 (= work + NM); backward
-    // inputs y and x (= work + 2 NM)
-    const double* t2 = P->work + NM;
-    const double* xv = P->work + 2 * NM;
-    const double* yv = P->work + 3 * NM;
-    auto make = [&](const SuperRow& R, bool fwd) {
+    // step arguments: forward inputs y (= work + 3 NM) and t2 (= work + NM), output y;
+    // backward inputs y and x (= work + 2 NM), output x
+    double* t2 = P->work + NM;
+    double* xv = P->work + 2 * NM;
+    double* yv = P->work + 3 * NM;
+    auto make = [&](const std::vector<int>& stage, bool fwd) {
         SuperStep st{};
-        st.nrow = R.nb;
-        int t = 0;
-        for (int i = 0; i < R.nb; ++i) {
-            st.first[i] = t;
-            for (int c = 0; c < R.nb + R.nprev; ++c) {
-                if (R.id[i][c] < 0) continue;
-                const double* v;
-                if (fwd)
-                    v = (c < R.nprev) ? yv + (size_t)(R.l0 - R.nprev + c) * N
-                                      : t2 + (size_t)(R.l0 + c - R.nprev) * N;
-                else
-                    v = (c < R.nb) ? yv + (size_t)(R.l0 + c) * N : xv + (size_t)(R.l0 + c) * N;
-                if (t >= kMaxSuperTerms) throw Error{SW_EINVAL, "super-row step has too many terms"};
-                st.blk[t] = Wb(R.id[i][c]);
-                st.vec[t] = v;
-                ++t;
+        int t = 0, row = 0;
+        for (int gi : stage) {
+            const SuperRow& R = fwd ? plan.fwd[gi] : plan.bwd[gi];
+            const int nb = (int)R.rows.size(), ne = (int)R.ext.size();
+            for (int i = 0; i < nb; ++i, ++row) {
+                st.first[row] = t;
+                st.out[row] = (fwd ? yv : xv) + (size_t)R.rows[i] * N;
+                for (int c = 0; c < nb + ne; ++c) {
+                    if (R.id[i][c] < 0) continue;
+                    const double* v;
+                    if (fwd)
+                        v = (c < ne) ? yv + (size_t)R.ext[c] * N : t2 + (size_t)R.rows[c - ne] * N;
+                    else
+                        v = (c < nb) ? yv + (size_t)R.rows[c] * N : xv + (size_t)R.ext[c - nb] * N;
+                    if (t >= kMaxSuperTerms)
+                        throw Error{SW_EINVAL, "super-row step has too many terms"};
+                    st.blk[t] = Wb(R.id[i][c]);
+                    st.vec[t] = v;
+                    ++t;
+                }
             }
         }
-        st.first[R.nb] = t;
+        st.nrow = row;
+        st.first[row] = t;
         return st;
     };
     P->fsteps.clear();
     P->bsteps.clear();
-    P->sl0.clear();
-    for (const SuperRow& R : plan.fwd) {
-        P->fsteps.push_back(make(R, true));
-        P->sl0.push_back(R.l0);
+    for (const auto& stage : plan.stages) P->fsteps.push_back(make(stage, true));
+    for (size_t k = plan.stages.size(); k-- > 0;) P->bsteps.push_back(make(plan.stages[k], false));
+}
+
+// Block LU of the band in the elimination order of make_order.  Step s < max(k, nB)
+// eliminates top row s and bottom row M-1-s together: one inversion launch for both
+// diagonal blocks, their products in the same GEMM launches.  The separator rows follow
+// one per step.  For a row l and each later-eliminated row i, j coupled to it:
+//   L_{i,l} = S_il Dinv_l,  G_{l,j} = Dinv_l S_lj,  S_ij -= S_il G_{l,j}.
+// G replaces S_lj in the launch of the Schur updates (which do not read it); L replaces
+// S_il in the next step's first launch (the Schur updates read S_il).  Products go to the
+// scratch of their chain and step parity.  The two chains meet only on the separator's
+// own blocks; a bottom update of a block that the top chain updates in the same step
+// goes to a launch of its own.
+void factor_band(sw_precond* P, const Order& o, hipStream_t s) {
+    const Geo& g = P->g;
+    const int q = P->q, M = g.M;
+    const size_t NN = (size_t)g.N * g.N;
+    auto Sb = [&](int r, int c) { return P->S + blk_off(P, r, c - r + q); };
+    double* gjt = P->tmp2;  // output blocks of an N > 192 inversion (two)
+    auto half = [&](int ch, int par) {
+        return P->tmp2 + NN * (2 + (size_t)(2 * ch + par) * 2 * q);
+    };
+    const int ns = std::max(o.k, o.nB);
+    std::vector<GemmJob> pendingL;
+    for (int step = 0; step < ns + q; ++step) {
+        int rows[2], nr = 0;
+        if (step < ns) {
+            if (step < o.k) rows[nr++] = step;
+            if (step < o.nB) rows[nr++] = M - 1 - step;
+        } else {
+            rows[nr++] = o.k + (step - ns);
+        }
+        if (nr == 2)
+            gj_inverse(g.N, Sb(rows[0], rows[0]), (size_t)(Sb(rows[1], rows[1]) - Sb(rows[0], rows[0])),
+                       2, P->info + 2 * step, gjt, P->tmp, s);
+        else
+            gj_inverse(g.N, Sb(rows[0], rows[0]), 0, 1, P->info + 2 * step, gjt, P->tmp, s);
+        std::vector<GemmJob> jobs1 = pendingL, jobs2, late;
+        pendingL.clear();
+        std::vector<const double*> top_targets;
+        for (int e = 0; e < nr; ++e) {
+            const int l = rows[e];
+            const int ch = (step < ns && l >= o.k) ? 1 : 0;
+            const int pl = o.rank[l];
+            std::vector<int> nbr;
+            for (int c = std::max(0, l - q); c <= std::min(M - 1, l + q); ++c)
+                if (c != l && o.rank[c] > pl) nbr.push_back(c);
+            if (nbr.empty()) continue;
+            double* sc = half(ch, step & 1);
+            const int nn = (int)nbr.size();
+            for (int a = 0; a < nn; ++a)
+                jobs1.push_back(GemmJob{Sb(nbr[a], l), Sb(l, l), nullptr, sc + (size_t)a * NN});
+            for (int b = 0; b < nn; ++b)
+                jobs1.push_back(GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
+            for (int a = 0; a < nn; ++a)
+                for (int b = 0; b < nn; ++b) {
+                    double* Sij = Sb(nbr[a], nbr[b]);
+                    const GemmJob j{Sb(nbr[a], l), sc + (size_t)(q + b) * NN, Sij, Sij};
+                    if (ch == 1 && std::find(top_targets.begin(), top_targets.end(), Sij) !=
+                                       top_targets.end())
+                        late.push_back(j);
+                    else
+                        jobs2.push_back(j);
+                    if (ch == 0) top_targets.push_back(Sij);
+                }
+            for (int b = 0; b < nn; ++b)
+                jobs2.push_back(GemmJob{sc + (size_t)(q + b) * NN, nullptr, nullptr, Sb(l, nbr[b])});
+            for (int a = 0; a < nn; ++a)
+                pendingL.push_back(GemmJob{sc + (size_t)a * NN, nullptr, nullptr, Sb(nbr[a], l)});
+        }
+        if (!jobs1.empty()) gemm_batched(g.N, 1.0, jobs1, s);
+        if (!jobs2.empty()) gemm_batched(g.N, -1.0, jobs2, s);
+        if (!late.empty()) gemm_batched(g.N, -1.0, late, s);
     }
-    for (const SuperRow& R : plan.bwd) P->bsteps.push_back(make(R, false));
+    if (!pendingL.empty()) gemm_batched(g.N, 1.0, pendingL, s);
 }
 }  // namespace
 
@@ -1541,9 +1705,9 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
     const int G = k3_chunks(g);
-    const size_t nw = plan_super(g, q, super_rows(g, q)).nblocks;
+    const size_t nw = choose_super(g, make_order(g.M, q), q).nblocks;
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
-                       gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 4,
+                       gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 8,
                        (size_t)G * g.ncol * 8, nw * NN * 8});
 }
 
@@ -1587,9 +1751,10 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->work = c.take<double>(4 * NM);
     P->tmp = c.take<double>(gj_work_size(g, q));
     P->tmp2 = c.take<double>(tmp2_blocks(g, q) * NN);
-    P->info = c.take<int>(g.M);
+    P->info = c.take<int>(2 * (size_t)g.M);
     double* part = c.take<double>((size_t)G * g.ncol);
-    const SuperPlan plan = plan_super(g, q, super_rows(g, q));
+    const Order order = make_order(g.M, q);
+    const SuperPlan plan = choose_super(g, order, q);
     P->sb = plan.b;
     P->W = c.take<double>(plan.nblocks * NN);
     try {
@@ -1600,49 +1765,11 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         const size_t total = (size_t)g.M * nb * NN;
         k_assemble<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>(
             g, q, P->k3, P->Wc, P->S);
-        if (q == 0) {
+        SW_HIP(hipMemsetAsync(P->info, 0, 2 * (size_t)g.M * sizeof(int), s));
+        if (q == 0)
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
-        } else {
-            // Step l: Dinv_l; L_{i,l} = S_{i,l} Dinv_l and G_{l,j} = Dinv_l U_{l,j} into the
-            // scratch half of l's parity; S_{i,j} -= S_{i,l} G_{l,j}.  G replaces U_{l,j} in the
-            // same launch as the Schur update (which does not read U); L replaces S_{i,l} in
-            // the next step's first launch (the Schur update reads S_{i,l}).
-            double* gjt = P->tmp2;  // output block of an N > 192 inversion
-            auto half = [&](int l) { return P->tmp2 + NN * (1 + (size_t)(l & 1) * 2 * q); };
-            std::vector<GemmJob> pendingL;
-            for (int l = 0; l < g.M; ++l) {
-                gj_inverse(g.N, P->S + blk_off(P, l, q), 0, 1, P->info + l, gjt, P->tmp, s);
-                const int hi = std::min(g.M - 1, l + q);
-                const int cnt = hi - l;
-                if (cnt == 0) continue;
-                double* sc = half(l);
-                std::vector<GemmJob> jobs = pendingL;
-                pendingL.clear();
-                for (int i = l + 1; i <= hi; ++i)
-                    jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
-                                           P->S + blk_off(P, l, q), nullptr,
-                                           sc + (size_t)(i - l - 1) * NN});
-                for (int j = l + 1; j <= hi; ++j)
-                    jobs.push_back(GemmJob{P->S + blk_off(P, l, q), P->S + blk_off(P, l, j - l + q),
-                                           nullptr, sc + (size_t)(q + j - l - 1) * NN});
-                gemm_batched(g.N, 1.0, jobs, s);
-                jobs.clear();
-                for (int i = l + 1; i <= hi; ++i)
-                    for (int j = l + 1; j <= hi; ++j) {
-                        double* Sij = P->S + blk_off(P, i, j - i + q);
-                        jobs.push_back(GemmJob{P->S + blk_off(P, i, l - i + q),
-                                               sc + (size_t)(q + j - l - 1) * NN, Sij, Sij});
-                    }
-                for (int j = l + 1; j <= hi; ++j)
-                    jobs.push_back(GemmJob{sc + (size_t)(q + j - l - 1) * NN, nullptr, nullptr,
-                                           P->S + blk_off(P, l, j - l + q)});
-                gemm_batched(g.N, -1.0, jobs, s);
-                for (int i = l + 1; i <= hi; ++i)
-                    pendingL.push_back(GemmJob{sc + (size_t)(i - l - 1) * NN, nullptr, nullptr,
-                                               P->S + blk_off(P, i, l - i + q)});
-            }
-            if (!pendingL.empty()) gemm_batched(g.N, 1.0, pendingL, s);
-        }
+        else
+            factor_band(P, order, s);
         if (q > 0 && P->sb > 1) {
             build_super(P, plan, s);
             capture_substitution(P);
@@ -1654,20 +1781,28 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
             P->fwd_cnt.resize(g.M);
             P->bwd_off.resize(g.M);
             P->bwd_cnt.resize(g.M);
-            for (int l = 0; l < g.M; ++l) {
-                P->fwd_off[l] = (int)tv.size();
-                for (int d = 1; d <= q && l - d >= 0; ++d)
-                    tv.push_back(GemvTerm{P->S + blk_off(P, l, q - d), tmpv + (size_t)(l - d) * N,
-                                          -1.0, 0.0});
-                P->fwd_cnt[l] = (int)tv.size() - P->fwd_off[l];
+            P->ord = order.ord;
+            // position p of the elimination order, block row l = ord[p]:
+            //   forward  y_l = t_l - sum L_{l,c} y_c over earlier c
+            //   backward x_l = Dinv_l y_l - sum G_{l,c} x_c over later c
+            for (int p = 0; p < g.M; ++p) {
+                const int l = order.ord[p];
+                P->fwd_off[p] = (int)tv.size();
+                for (int c = std::max(0, l - q); c <= std::min(g.M - 1, l + q); ++c)
+                    if (order.rank[c] < p)
+                        tv.push_back(GemvTerm{P->S + blk_off(P, l, c - l + q),
+                                              tmpv + (size_t)c * N, -1.0, 0.0});
+                P->fwd_cnt[p] = (int)tv.size() - P->fwd_off[p];
             }
-            for (int l = 0; l < g.M; ++l) {
-                P->bwd_off[l] = (int)tv.size();
+            for (int p = 0; p < g.M; ++p) {
+                const int l = order.ord[p];
+                P->bwd_off[p] = (int)tv.size();
                 tv.push_back(GemvTerm{P->S + blk_off(P, l, q), tmpv + (size_t)l * N, 1.0, 0.0});
-                for (int d = 1; d <= q && l + d < g.M; ++d)
-                    tv.push_back(GemvTerm{P->S + blk_off(P, l, q + d), xv + (size_t)(l + d) * N,
-                                          -1.0, 0.0});
-                P->bwd_cnt[l] = (int)tv.size() - P->bwd_off[l];
+                for (int c = std::max(0, l - q); c <= std::min(g.M - 1, l + q); ++c)
+                    if (order.rank[c] > p)
+                        tv.push_back(GemvTerm{P->S + blk_off(P, l, c - l + q),
+                                              xv + (size_t)c * N, -1.0, 0.0});
+                P->bwd_cnt[p] = (int)tv.size() - P->bwd_off[p];
             }
             SW_HIP(hipMalloc(&P->terms, tv.size() * sizeof(GemvTerm)));
             SW_HIP(hipMemcpy(P->terms, tv.data(), tv.size() * sizeof(GemvTerm),
@@ -1702,29 +1837,27 @@ void enqueue_substitution(const sw_precond* P, hipStream_t s) {
     double* s2 = P->work + 2 * NM;
     double* tmp = P->work + 3 * NM;
     if (P->sb > 1) {
-        // y in tmp, x in s2 (the step arguments point there)
-        for (size_t k = 0; k < P->fsteps.size(); ++k) {
-            const SuperStep& st = P->fsteps[k];
-            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st,
-                                                                 tmp + (size_t)P->sl0[k] * N);
-        }
-        for (size_t k = P->bsteps.size(); k-- > 0;) {
-            const SuperStep& st = P->bsteps[k];
-            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st,
-                                                                 s2 + (size_t)P->sl0[k] * N);
-        }
+        // y in tmp, x in s2 (the step arguments point there); backward steps are stored
+        // in launch order
+        for (const SuperStep& st : P->fsteps)
+            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st);
+        for (const SuperStep& st : P->bsteps)
+            k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st);
         return;
     }
     const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);
     const unsigned blocks = (unsigned)((N * 64 + 255) / 256);
-    // forward: y_l = t_l - sum_d L_{l,l-d} y_{l-d}   (y in tmp)
-    for (int l = 0; l < g.M; ++l)
-        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->fwd_off[l], P->fwd_cnt[l],
+    // forward in elimination order (y in tmp), backward in reverse (x in s2)
+    for (int p = 0; p < g.M; ++p) {
+        const int l = P->ord[p];
+        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->fwd_off[p], P->fwd_cnt[p],
                                            t2 + (size_t)l * N, tmp + (size_t)l * N);
-    // backward: x_l = Dinv_l y_l - sum_d G_{l,l+d} x_{l+d}   (x in s2)
-    for (int l = g.M - 1; l >= 0; --l)
-        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->bwd_off[l], P->bwd_cnt[l], nullptr,
+    }
+    for (int p = g.M - 1; p >= 0; --p) {
+        const int l = P->ord[p];
+        k_band_step<<<blocks, 256, 0, s>>>(N, terms + P->bwd_off[p], P->bwd_cnt[p], nullptr,
                                            s2 + (size_t)l * N);
+    }
 }
 
 // Capture the substitution launches into an executable graph (kernel nodes only).

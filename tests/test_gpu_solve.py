@@ -175,3 +175,23 @@ def test_preconditioner_wide_blocks_match_dense_solve(N, M):
         res = _backward_error(Pm, x, b)
         log(f"N={N} M={M} q={q}: backward err {res:.2e}")
         assert res <= 1e-12  # normwise backward error, ~4 n eps at n = 2410
+
+
+@pytest.mark.parametrize("N,M,q", [(31, 40, 8), (31, 60, 10), (15, 20, 19), (41, 13, 6),
+                                   (41, 14, 3), (21, 9, 2)])
+def test_preconditioner_band_orders_match_dense_solve(N, M, q):
+    """The band is eliminated from both ends with q separator rows last.  Cases: a top and
+    a bottom super row too large to share a launch (31 x 40, q = 8), a separator super row
+    that has to shrink to fit (31 x 60, q = 10), q = M - 1 (no bottom chain), and M - q
+    odd and even (chains of equal and unequal length)."""
+    p = api.Problem(N, M, -10.0, 8.0, 3.0, F=0.75, eps=0.1)
+    op = oprob(p)
+    Pm = OL.BlockPreconditioner(op, q).matrix()
+    P = api.Preconditioner(p, q)
+    for k in range(2):
+        b = np.random.default_rng(1000 * N + M + k).standard_normal(p.n_unknowns)
+        x = host(P.apply(dev(b)))
+        res = _backward_error(Pm, x, b)
+        log(f"N={N} M={M} q={q} rhs {k}: backward err {res:.2e}")
+        assert res <= 1e-12
+    P.close()

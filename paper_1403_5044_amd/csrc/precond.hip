@@ -26,7 +26,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
+#include <functional>
 #include <vector>
 
 namespace sw {
@@ -1515,15 +1517,19 @@ void fill_batched(int N, const std::vector<FillJob>& jobs, hipStream_t s) {
     }
 }
 
-// Form W and W' from the band factors in P->S and record the step arguments.
-void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
+// Form W and W' of the given super rows from the band factors in P->S.  Only the
+// factor blocks stored in the super rows' own block rows are read.  The forward and
+// backward levels of one depth share a launch.
+void super_operators(sw_precond* P, const SuperPlan& plan, const std::vector<int>& rows_of,
+                     hipStream_t s) {
     const Geo& g = P->g;
     const int q = P->q, N = g.N;
-    const size_t NN = (size_t)N * N, NM = g.NM;
+    const size_t NN = (size_t)N * N;
     auto Wb = [&](int id) { return P->W + (size_t)id * NN; };
     auto Sb = [&](int r, int c) { return P->S + blk_off(P, r, c - r + q); };
     std::vector<FillJob> fills;
-    for (const SuperRow& R : plan.fwd) {
+    for (int gi : rows_of) {
+        const SuperRow& R = plan.fwd[gi];
         const int nb = (int)R.rows.size(), ne = (int)R.ext.size();
         for (int i = 0; i < nb; ++i)
             for (int c = 0; c < nb + ne; ++c) {
@@ -1538,7 +1544,8 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
                 fills.push_back(j);
             }
     }
-    for (const SuperRow& R : plan.bwd) {
+    for (int gi : rows_of) {
+        const SuperRow& R = plan.bwd[gi];
         const int nb = (int)R.rows.size(), ne = (int)R.ext.size();
         for (int i = 0; i < nb; ++i)
             for (int c = 0; c < nb + ne; ++c) {
@@ -1555,26 +1562,23 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
             }
     }
     fill_batched(N, fills, s);
-    // forward levels: W_i -= L_{R_i, R_{i-d}} W_{i-d}
-    for (int i = 1; i < plan.b; ++i)
-        for (int d = 1; d <= std::min(q, i); ++d) {
-            std::vector<GemmJob> jobs;
-            for (const SuperRow& R : plan.fwd) {
-                if (i >= (int)R.rows.size() || !coupled(R.rows[i], R.rows[i - d], q)) continue;
-                for (size_t c = 0; c < R.id[i].size(); ++c) {
-                    const int src = R.id[i - d][c];
-                    if (src < 0) continue;
-                    double* dst = Wb(R.id[i][c]);
-                    jobs.push_back(GemmJob{Sb(R.rows[i], R.rows[i - d]), Wb(src), dst, dst});
-                }
-            }
-            gemm_batched(N, -1.0, jobs, s);
-        }
-    // backward levels (i = nb - 1 - e): W'_i -= G_{R_i, R_{i+d}} W'_{i+d}
+    // level e, depth d: forward W_e -= L_{R_e, R_{e-d}} W_{e-d}; backward (i = nb - 1 - e)
+    // W'_i -= G_{R_i, R_{i+d}} W'_{i+d}
     for (int e = 1; e < plan.b; ++e)
         for (int d = 1; d <= std::min(q, e); ++d) {
             std::vector<GemmJob> jobs;
-            for (const SuperRow& R : plan.bwd) {
+            for (int gi : rows_of) {
+                const SuperRow& R = plan.fwd[gi];
+                if (e >= (int)R.rows.size() || !coupled(R.rows[e], R.rows[e - d], q)) continue;
+                for (size_t c = 0; c < R.id[e].size(); ++c) {
+                    const int src = R.id[e - d][c];
+                    if (src < 0) continue;
+                    double* dst = Wb(R.id[e][c]);
+                    jobs.push_back(GemmJob{Sb(R.rows[e], R.rows[e - d]), Wb(src), dst, dst});
+                }
+            }
+            for (int gi : rows_of) {
+                const SuperRow& R = plan.bwd[gi];
                 const int i = (int)R.rows.size() - 1 - e;
                 if (i < 0 || !coupled(R.rows[i], R.rows[i + d], q)) continue;
                 for (size_t c = 0; c < R.id[i].size(); ++c) {
@@ -1586,8 +1590,16 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
             }
             gemm_batched(N, -1.0, jobs, s);
         }
-    // step arguments: forward inputs y (= work + 3 NM) and t2 (= work + NM), output y;
-    // backward inputs y and x (= work + 2 NM), output x
+}
+
+// Kernel arguments of the super-row steps: forward inputs y (= work + 3 NM) and t2
+// (= work + NM), output y; backward inputs y and x (= work + 2 NM), output x.  Backward
+// steps are stored in launch order.
+void super_steps(sw_precond* P, const SuperPlan& plan) {
+    const Geo& g = P->g;
+    const int N = g.N;
+    const size_t NN = (size_t)N * N, NM = g.NM;
+    auto Wb = [&](int id) { return P->W + (size_t)id * NN; };
     double* t2 = P->work + NM;
     double* xv = P->work + 2 * NM;
     double* yv = P->work + 3 * NM;
@@ -1625,6 +1637,14 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
     for (size_t k = plan.stages.size(); k-- > 0;) P->bsteps.push_back(make(plan.stages[k], false));
 }
 
+// Factorisation step that eliminates block row l.
+int elim_step(const Order& o, int l) {
+    const int p = o.rank[l];
+    if (p < o.k) return p;
+    if (p < o.k + o.nB) return p - o.k;
+    return std::max(o.k, o.nB) + (p - o.k - o.nB);
+}
+
 // Block LU of the band in the elimination order of make_order.  Step s < max(k, nB)
 // eliminates top row s and bottom row M-1-s together: one inversion launch for both
 // diagonal blocks, their products in the same GEMM launches.  The separator rows follow
@@ -1634,8 +1654,10 @@ void build_super(sw_precond* P, const SuperPlan& plan, hipStream_t s) {
 // S_il in the next step's first launch (the Schur updates read S_il).  Products go to the
 // scratch of their chain and step parity.  The two chains meet only on the separator's
 // own blocks; a bottom update of a block that the top chain updates in the same step
-// goes to a launch of its own.
-void factor_band(sw_precond* P, const Order& o, hipStream_t s) {
+// goes to a launch of its own.  done(step) runs after each step's launches are enqueued,
+// and done(INT_MAX) after the last.
+void factor_band(sw_precond* P, const Order& o, hipStream_t s,
+                 const std::function<void(int)>& done) {
     const Geo& g = P->g;
     const int q = P->q, M = g.M;
     const size_t NN = (size_t)g.N * g.N;
@@ -1695,8 +1717,10 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s) {
         if (!jobs1.empty()) gemm_batched(g.N, 1.0, jobs1, s);
         if (!jobs2.empty()) gemm_batched(g.N, -1.0, jobs2, s);
         if (!late.empty()) gemm_batched(g.N, -1.0, late, s);
+        if (step + 1 < ns + q) done(step);
     }
     if (!pendingL.empty()) gemm_batched(g.N, 1.0, pendingL, s);
+    done(INT_MAX);
 }
 }  // namespace
 
@@ -1721,6 +1745,66 @@ bool precond_matches(const sw_precond* P, const Geo& g) {
 namespace {
 void capture_substitution(sw_precond* P);
 }
+
+namespace {
+// The band factorisation on s, and the super-row operators of each stage on a helper
+// stream as soon as the step that eliminates the stage's last rows is enqueued: the
+// chain of inversions leaves most of the device idle.  s then waits for the helper.
+void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, hipStream_t s) {
+    std::vector<int> ready(plan.stages.size(), 0);
+    for (size_t k = 0; k < plan.stages.size(); ++k)
+        for (int gi : plan.stages[k])
+            for (int r : plan.fwd[gi].rows) ready[k] = std::max(ready[k], elim_step(o, r));
+    hipStream_t aux = nullptr;
+    if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        aux = nullptr;
+    }
+    std::vector<hipEvent_t> evs;
+    auto cleanup = [&]() {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamDestroy(aux);
+    };
+    try {
+        size_t next = 0;  // stages are ready in order
+        std::vector<size_t> order_by_ready(plan.stages.size());
+        for (size_t k = 0; k < order_by_ready.size(); ++k) order_by_ready[k] = k;
+        std::stable_sort(order_by_ready.begin(), order_by_ready.end(),
+                         [&](size_t a, size_t b) { return ready[a] < ready[b]; });
+        factor_band(P, o, s, [&](int step) {
+            while (next < order_by_ready.size() && ready[order_by_ready[next]] <= step) {
+                const auto& stage = plan.stages[order_by_ready[next++]];
+                if (!aux) continue;  // built on s after the factorisation
+                hipEvent_t e = nullptr;
+                SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                evs.push_back(e);
+                SW_HIP(hipEventRecord(e, s));
+                SW_HIP(hipStreamWaitEvent(aux, e, 0));
+                super_operators(P, plan, stage, aux);
+            }
+        });
+        if (aux) {
+            hipEvent_t e = nullptr;
+            SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            evs.push_back(e);
+            SW_HIP(hipEventRecord(e, aux));
+            SW_HIP(hipStreamWaitEvent(s, e, 0));
+        } else {
+            std::vector<int> all(plan.fwd.size());
+            for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+            super_operators(P, plan, all, s);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        if (aux) (void)hipStreamSynchronize(aux);
+        cleanup();
+        throw;
+    }
+    // the helper's stream and events are released once s has passed the join
+    SW_HIP(hipStreamSynchronize(s));
+    cleanup();
+}
+}  // namespace
 
 sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     Geo g = g0;
@@ -1766,14 +1850,19 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         k_assemble<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>(
             g, q, P->k3, P->Wc, P->S);
         SW_HIP(hipMemsetAsync(P->info, 0, 2 * (size_t)g.M * sizeof(int), s));
+        if (q > 0 && P->sb > 1) {
+            // the step arguments and the captured launches only hold pointers, so they
+            // are recorded before the operators are computed
+            super_steps(P, plan);
+            capture_substitution(P);
+        }
         if (q == 0)
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
+        else if (P->sb > 1)
+            factor_with_super(P, order, plan, s);
         else
-            factor_band(P, order, s);
-        if (q > 0 && P->sb > 1) {
-            build_super(P, plan, s);
-            capture_substitution(P);
-        } else if (q > 0) {
+            factor_band(P, order, s, [](int) {});
+        if (q > 0 && P->sb <= 1) {
             std::vector<GemvTerm> tv;
             double* tmpv = P->work + 3 * NM;
             double* xv = P->work + 2 * NM;
@@ -1810,8 +1899,9 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
             capture_substitution(P);
         }
         SW_HIP(hipGetLastError());
-        std::vector<int> info(g.M);
-        SW_HIP(hipMemcpyAsync(info.data(), P->info, g.M * sizeof(int), hipMemcpyDeviceToHost, s));
+        std::vector<int> info(2 * (size_t)g.M);
+        SW_HIP(hipMemcpyAsync(info.data(), P->info, info.size() * sizeof(int),
+                              hipMemcpyDeviceToHost, s));
         SW_HIP(hipStreamSynchronize(s));
         for (int v : info)
             if (v != 0) throw Error{SW_ENONFINITE, "preconditioner: singular diagonal block"};

@@ -117,85 +117,82 @@ __global__ void k_wmat(Geo g, double* __restrict__ Wc) {
     }
 }
 
-// sum_{i,j} w(i,j) K3(i,j; k,l) for each collocation point, split over row chunks.
-__global__ __launch_bounds__(256) void k_k3_partial(Geo g, int G, double* __restrict__ part) {
-    const int ntile = (g.ncol + 255) / 256;
-    const int tile = blockIdx.x % ntile;
-    const int chunk = blockIdx.x / ntile;
-    const int c = tile * 256 + threadIdx.x;
+// sum_{i,j} w(i,j) K3(i,j; k,l) for each collocation point (k, l).  The sum over i at
+// a fixed row offset depends only on k and that offset, so it is formed once per offset:
+//   R[o][k] = sum_i w_i / sqrt(((i - k) - 1/2)^2 dx^2 + (o dy)^2),   o = 0 .. 2M-2,
+// and then k3(k, l) = dx dy sum_j w_j (R[|j - l|][k] + R[j + l][k]).
+__global__ __launch_bounds__(256) void k_k3_rows(Geo g, double* __restrict__ R) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int o = blockIdx.y;
+    if (k >= g.Nc) return;
+    const double dy = (double)o * g.dy, dy2 = dy * dy;
+    double row = 0.0;
+    for (int i = 0; i < g.N; ++i) {
+        const double dx = ((double)(i - k) - 0.5) * g.dx;
+        row = fma(weight1d(i, g.N, g.weights), rsq_exact(dx * dx + dy2), row);
+    }
+    R[(size_t)o * g.Nc + k] = row;
+}
+
+__global__ __launch_bounds__(256) void k_k3_sum(Geo g, const double* __restrict__ R,
+                                                double* __restrict__ k3) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= g.ncol) return;
     const int l = c / g.Nc;
     const int k = c - l * g.Nc;
-    const int j0 = (int)((long long)chunk * g.M / G), j1 = (int)((long long)(chunk + 1) * g.M / G);
     double s = 0.0;
-    for (int j = j0; j < j1; ++j) {
-        const double dy = (double)(j - l) * g.dy, dyp = (double)(j + l) * g.dy;
-        const double dy2 = dy * dy, dyp2 = dyp * dyp;
-        const double wy = g.dx * g.dy * weight1d(j, g.M, g.weights);
-        double row = 0.0;
-        for (int i = 0; i < g.N; ++i) {
-            const double dx = ((double)(i - k) - 0.5) * g.dx;
-            const double dx2 = dx * dx;
-            row = fma(weight1d(i, g.N, g.weights), rsq_exact(dx2 + dy2) + rsq_exact(dx2 + dyp2),
-                      row);
-        }
-        s = fma(wy, row, s);
+    for (int j = 0; j < g.M; ++j) {
+        const int o = j >= l ? j - l : l - j;
+        s = fma(weight1d(j, g.M, g.weights),
+                R[(size_t)o * g.Nc + k] + R[(size_t)(j + l) * g.Nc + k], s);
     }
-    part[(size_t)chunk * g.ncol + c] = s;
+    k3[c] = g.dx * g.dy * s;
 }
 
-__global__ void k_k3_final(Geo g, int G, const double* __restrict__ part, double* __restrict__ k3) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncol) return;
-    double s = 0.0;
-    for (int q = 0; q < G; ++q) s += part[(size_t)q * g.ncol + c];
-    k3[c] = s;
-}
-
-// Entries of the banded Schur complement before factorisation.
-// One workgroup per 16 rows of one band block (l, d): grid (M nb, ceil(N / 16)),
-// threads over the columns n.
+// Entries of the banded Schur complement before factorisation: grid x over the N x N
+// entries of one band block, grid y over the blocks (l, d) (block b = l (2q+1) + d).
 __global__ __launch_bounds__(256) void k_assemble(Geo g, int q, const double* __restrict__ k3,
                                                   const double* __restrict__ Wc,
                                                   double* __restrict__ S) {
     const int nb = 2 * q + 1;
-    const size_t NN = (size_t)g.N * g.N;
-    const size_t total = (size_t)g.M * nb * NN;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int n = (int)(e % g.N);
-        const int r = (int)((e / g.N) % g.N);
-        const int d = (int)((e / NN) % nb);
-        const int l = (int)(e / (NN * nb));
-        const int m = l + d - q;
-        double v = 0.0;
-        if (m >= 0 && m < g.M) {
-            if (r == 0) {
-                if (m == l) {
-                    if (n == 0) v = g.nu - g.x1 / g.dx;
-                    if (n == 1) v = g.x1 / g.dx;
-                }
-            } else {
-                const int k = r - 1;
-                const double dx = ((double)(n - k) - 0.5) * g.dx;
-                const double dy = (double)(m - l) * g.dy, dyp = (double)(m + l) * g.dy;
-                const double K3 = 1.0 / sqrt(dx * dx + dy * dy) + 1.0 / sqrt(dx * dx + dyp * dyp);
-                const double w =
-                    g.dx * g.dy * weight1d(n, g.N, g.weights) * weight1d(m, g.M, g.weights);
-                v = -w * K3;
-                if (m == l) {
-                    if (n == k || n == k + 1) {
-                        const double xs = g.x1 + (k + 0.5) * g.dx;
-                        const double ys = l * g.dy;
-                        const double Il =
-                            closed_form_I(1.0, 0.0, 1.0, 4.0, xs - g.x1, g.xN - xs, ys, g.yM);
-                        v += 0.5 * (k3[(size_t)l * g.Nc + k] - Il);
+    const unsigned N = g.N, NN = N * N;
+    for (int b = blockIdx.y; b < g.M * nb; b += gridDim.y) {
+        const int l = b / nb;
+        const int m = l + (b - l * nb) - q;
+        double* Sb = S + (size_t)b * NN;
+        const bool inside = m >= 0 && m < g.M;
+        const double dy = (double)(m - l) * g.dy, dyp = (double)(m + l) * g.dy;
+        const double dy2 = dy * dy, dyp2 = dyp * dyp;
+        const double wm = g.dx * g.dy * weight1d(inside ? m : 0, g.M, g.weights);
+        for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < NN; e += gridDim.x * 256) {
+            const int r = (int)(e / N), n = (int)(e - (unsigned)r * N);
+            double v = 0.0;
+            if (inside) {
+                if (r == 0) {
+                    if (m == l) {
+                        if (n == 0) v = g.nu - g.x1 / g.dx;
+                        if (n == 1) v = g.x1 / g.dx;
                     }
-                    v -= Wc[(size_t)r * g.N + n];
+                } else {
+                    const int k = r - 1;
+                    const double dx = ((double)(n - k) - 0.5) * g.dx;
+                    const double dx2 = dx * dx;
+                    const double K3 = rsq_exact(dx2 + dy2) + rsq_exact(dx2 + dyp2);
+                    v = -(wm * weight1d(n, g.N, g.weights)) * K3;
+                    if (m == l) {
+                        if (n == k || n == k + 1) {
+                            const double xs = g.x1 + (k + 0.5) * g.dx;
+                            const double ys = l * g.dy;
+                            const double Il =
+                                closed_form_I(1.0, 0.0, 1.0, 4.0, xs - g.x1, g.xN - xs, ys, g.yM);
+                            v += 0.5 * (k3[(size_t)l * g.Nc + k] - Il);
+                        }
+                        v -= Wc[(size_t)r * g.N + n];
+                    }
                 }
             }
+            Sb[e] = v;
         }
-        S[e] = v;
     }
 }
 
@@ -1328,10 +1325,8 @@ size_t gj_work_size(const Geo& g, int q) {
     return std::max(NN, gj_work_doubles(g.N, q == 0 ? g.M : 2));
 }
 
-int k3_chunks(const Geo& g) {
-    const int ntile = (g.ncol + 255) / 256;
-    return std::max(1, std::min(g.M, (4096 + ntile - 1) / ntile));
-}
+// row sums of the K3 sum, one per row offset
+size_t k3_rows_doubles(const Geo& g) { return (size_t)(2 * g.M - 1) * g.Nc; }
 }  // namespace
 
 // ---- elimination order ----------------------------------------------------------------
@@ -1728,11 +1723,10 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const int q = std::max(0, std::min(q_req, g.M - 1));
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
-    const int G = k3_chunks(g);
     const size_t nw = choose_super(g, make_order(g.M, q), q).nblocks;
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
                        gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 8,
-                       (size_t)G * g.ncol * 8, nw * NN * 8});
+                       k3_rows_doubles(g) * 8, nw * NN * 8});
 }
 
 size_t precond_bytes(const sw_precond* P) { return P ? P->bytes : 0; }
@@ -1747,62 +1741,67 @@ void capture_substitution(sw_precond* P);
 }
 
 namespace {
-// The band factorisation on s, and the super-row operators of each stage on a helper
+// A helper stream and the events that order it after s; released only once s (which
+// waits for the helper at the end) has been synchronised, or after draining both.
+struct SideStream {
+    hipStream_t aux = nullptr;
+    std::vector<hipEvent_t> evs;
+    SideStream() = default;
+    void open() {  // without a helper stream the work stays on s
+        if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            aux = nullptr;
+        }
+    }
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
+    hipEvent_t event() {
+        hipEvent_t e = nullptr;
+        SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        evs.push_back(e);
+        return e;
+    }
+    ~SideStream() {
+        if (aux) (void)hipStreamSynchronize(aux);
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
+};
+
+// The band factorisation on s, and the super-row operators of each stage on the helper
 // stream as soon as the step that eliminates the stage's last rows is enqueued: the
 // chain of inversions leaves most of the device idle.  s then waits for the helper.
-void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, hipStream_t s) {
+void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, SideStream& side,
+                       hipStream_t s) {
+    side.open();
     std::vector<int> ready(plan.stages.size(), 0);
     for (size_t k = 0; k < plan.stages.size(); ++k)
         for (int gi : plan.stages[k])
             for (int r : plan.fwd[gi].rows) ready[k] = std::max(ready[k], elim_step(o, r));
-    hipStream_t aux = nullptr;
-    if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        aux = nullptr;
-    }
-    std::vector<hipEvent_t> evs;
-    auto cleanup = [&]() {
-        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-        if (aux) (void)hipStreamDestroy(aux);
-    };
-    try {
-        size_t next = 0;  // stages are ready in order
-        std::vector<size_t> order_by_ready(plan.stages.size());
-        for (size_t k = 0; k < order_by_ready.size(); ++k) order_by_ready[k] = k;
-        std::stable_sort(order_by_ready.begin(), order_by_ready.end(),
-                         [&](size_t a, size_t b) { return ready[a] < ready[b]; });
-        factor_band(P, o, s, [&](int step) {
-            while (next < order_by_ready.size() && ready[order_by_ready[next]] <= step) {
-                const auto& stage = plan.stages[order_by_ready[next++]];
-                if (!aux) continue;  // built on s after the factorisation
-                hipEvent_t e = nullptr;
-                SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-                evs.push_back(e);
-                SW_HIP(hipEventRecord(e, s));
-                SW_HIP(hipStreamWaitEvent(aux, e, 0));
-                super_operators(P, plan, stage, aux);
-            }
-        });
-        if (aux) {
-            hipEvent_t e = nullptr;
-            SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            evs.push_back(e);
-            SW_HIP(hipEventRecord(e, aux));
-            SW_HIP(hipStreamWaitEvent(s, e, 0));
-        } else {
-            std::vector<int> all(plan.fwd.size());
-            for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
-            super_operators(P, plan, all, s);
+    std::vector<size_t> by_ready(plan.stages.size());
+    for (size_t k = 0; k < by_ready.size(); ++k) by_ready[k] = k;
+    std::stable_sort(by_ready.begin(), by_ready.end(),
+                     [&](size_t a, size_t b) { return ready[a] < ready[b]; });
+    size_t next = 0;
+    factor_band(P, o, s, [&](int step) {
+        while (next < by_ready.size() && ready[by_ready[next]] <= step) {
+            const auto& stage = plan.stages[by_ready[next++]];
+            if (!side.aux) continue;  // built on s after the factorisation
+            hipEvent_t e = side.event();
+            SW_HIP(hipEventRecord(e, s));
+            SW_HIP(hipStreamWaitEvent(side.aux, e, 0));
+            super_operators(P, plan, stage, side.aux);
         }
-    } catch (...) {
-        (void)hipStreamSynchronize(s);
-        if (aux) (void)hipStreamSynchronize(aux);
-        cleanup();
-        throw;
+    });
+    if (side.aux) {
+        hipEvent_t e = side.event();
+        SW_HIP(hipEventRecord(e, side.aux));
+        SW_HIP(hipStreamWaitEvent(s, e, 0));
+    } else {
+        std::vector<int> all(plan.fwd.size());
+        for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+        super_operators(P, plan, all, s);
     }
-    // the helper's stream and events are released once s has passed the join
-    SW_HIP(hipStreamSynchronize(s));
-    cleanup();
 }
 }  // namespace
 
@@ -1812,7 +1811,6 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     const int q = std::max(0, std::min(q_req, g.M - 1));
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
-    const int G = k3_chunks(g);
     const size_t bytes = precond_bytes_estimate(g, q);
     (void)N;
     auto* P = new sw_precond();
@@ -1836,33 +1834,30 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->tmp = c.take<double>(gj_work_size(g, q));
     P->tmp2 = c.take<double>(tmp2_blocks(g, q) * NN);
     P->info = c.take<int>(2 * (size_t)g.M);
-    double* part = c.take<double>((size_t)G * g.ncol);
+    double* k3rows = c.take<double>(k3_rows_doubles(g));
     const Order order = make_order(g.M, q);
     const SuperPlan plan = choose_super(g, order, q);
     P->sb = plan.b;
     P->W = c.take<double>(plan.nblocks * NN);
     try {
         k_wmat<<<(g.N + 63) / 64, 64, 0, s>>>(g, P->Wc);
-        const int ntile = (g.ncol + 255) / 256;
-        k_k3_partial<<<ntile * G, 256, 0, s>>>(g, G, part);
-        k_k3_final<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, G, part, P->k3);
-        const size_t total = (size_t)g.M * nb * NN;
-        k_assemble<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>(
-            g, q, P->k3, P->Wc, P->S);
+        k_k3_rows<<<dim3((g.Nc + 255) / 256, 2 * g.M - 1), 256, 0, s>>>(g, k3rows);
+        k_k3_sum<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, k3rows, P->k3);
+        const dim3 ag((unsigned)std::min<size_t>((NN + 1023) / 1024, 4096),
+                      (unsigned)std::min(g.M * nb, 65535));
+        k_assemble<<<ag, 256, 0, s>>>(g, q, P->k3, P->Wc, P->S);
         SW_HIP(hipMemsetAsync(P->info, 0, 2 * (size_t)g.M * sizeof(int), s));
-        if (q > 0 && P->sb > 1) {
-            // the step arguments and the captured launches only hold pointers, so they
-            // are recorded before the operators are computed
-            super_steps(P, plan);
-            capture_substitution(P);
-        }
+        SideStream side;  // declared before the synchronisation below, released after it
         if (q == 0)
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
         else if (P->sb > 1)
-            factor_with_super(P, order, plan, s);
+            factor_with_super(P, order, plan, side, s);
         else
             factor_band(P, order, s, [](int) {});
-        if (q > 0 && P->sb <= 1) {
+        if (q > 0 && P->sb > 1) {
+            super_steps(P, plan);
+            capture_substitution(P);
+        } else if (q > 0) {
             std::vector<GemvTerm> tv;
             double* tmpv = P->work + 3 * NM;
             double* xv = P->work + 2 * NM;

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void k_quot(int n, const double* __restri
 
 // Final pass of norm_inf_2 on z (partials in work), the JVP step from it (as k_jvp_h),
 // and out = u + step z.  Workgroup 0 stores the norms of z and h = [step, 1/step].
-__global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B, const double* __restrict__ work,
+__global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B,
+                                                         const double* __restrict__ work,
                                                          const double* __restrict__ norms_u,
                                                          double sqrt_eps, double sqrt_n,
                                                          double* __restrict__ norms_z,

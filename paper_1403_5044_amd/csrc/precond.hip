@@ -1671,11 +1671,10 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s,
         } else {
             rows[nr++] = o.k + (step - ns);
         }
-        if (nr == 2)
-            gj_inverse(g.N, Sb(rows[0], rows[0]), (size_t)(Sb(rows[1], rows[1]) - Sb(rows[0], rows[0])),
-                       2, P->info + 2 * step, gjt, P->tmp, s);
-        else
-            gj_inverse(g.N, Sb(rows[0], rows[0]), 0, 1, P->info + 2 * step, gjt, P->tmp, s);
+        // the bottom row's diagonal block is at a higher address than the top row's
+        double* d0 = Sb(rows[0], rows[0]);
+        const size_t stride = (nr == 2) ? (size_t)(Sb(rows[1], rows[1]) - d0) : 0;
+        gj_inverse(g.N, d0, stride, nr, P->info + 2 * step, gjt, P->tmp, s);
         std::vector<GemmJob> jobs1 = pendingL, jobs2, late;
         pendingL.clear();
         std::vector<const double*> top_targets;
@@ -1692,7 +1691,8 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s,
             for (int a = 0; a < nn; ++a)
                 jobs1.push_back(GemmJob{Sb(nbr[a], l), Sb(l, l), nullptr, sc + (size_t)a * NN});
             for (int b = 0; b < nn; ++b)
-                jobs1.push_back(GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
+                jobs1.push_back(
+                    GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
             for (int a = 0; a < nn; ++a)
                 for (int b = 0; b < nn; ++b) {
                     double* Sij = Sb(nbr[a], nbr[b]);
@@ -1705,7 +1705,8 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s,
                     if (ch == 0) top_targets.push_back(Sij);
                 }
             for (int b = 0; b < nn; ++b)
-                jobs2.push_back(GemmJob{sc + (size_t)(q + b) * NN, nullptr, nullptr, Sb(l, nbr[b])});
+                jobs2.push_back(
+                    GemmJob{sc + (size_t)(q + b) * NN, nullptr, nullptr, Sb(l, nbr[b])});
             for (int a = 0; a < nn; ++a)
                 pendingL.push_back(GemmJob{sc + (size_t)a * NN, nullptr, nullptr, Sb(nbr[a], l)});
         }

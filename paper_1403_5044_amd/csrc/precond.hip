@@ -29,6 +29,7 @@
 #include <climits>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 namespace sw {
@@ -66,6 +67,7 @@ struct sw_precond {
     std::vector<sw::SuperStep> fsteps, bsteps;  // kernel arguments of the super-row steps
     std::vector<int> ord;                       // elimination order of the block rows
     size_t bytes = 0;
+    size_t block = 0;  // size of the device block at base (>= bytes)
     int device = -1;
 };
 
@@ -1742,30 +1744,70 @@ void capture_substitution(sw_precond* P);
 }
 
 namespace {
-// A helper stream and the events that order it after s; released only once s (which
-// waits for the helper at the end) has been synchronised, or after draining both.
+// Helper streams and events are reused across builds: creating and destroying them
+// costs the host about as much as a factorisation step.  They live until the process
+// ends (one per concurrent build and device).
+struct SidePool {
+    std::mutex mu;
+    std::vector<std::pair<int, hipStream_t>> streams;
+    std::vector<std::pair<int, hipEvent_t>> events;
+};
+SidePool& side_pool() {
+    static SidePool* p = new SidePool();  // never destroyed: used until exit
+    return *p;
+}
+
+// A helper stream and the events that order it after s.  It goes back to the pool only
+// once s (which waits for the helper at the end) has been synchronised, or after
+// draining both.
 struct SideStream {
+    int dev = -1;
     hipStream_t aux = nullptr;
     std::vector<hipEvent_t> evs;
     SideStream() = default;
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
     void open() {  // without a helper stream the work stays on s
-        if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+        if (aux) return;
+        SW_HIP(hipGetDevice(&dev));
+        {
+            SidePool& p = side_pool();
+            std::lock_guard<std::mutex> lk(p.mu);
+            for (size_t i = 0; i < p.streams.size(); ++i)
+                if (p.streams[i].first == dev) {
+                    aux = p.streams[i].second;
+                    p.streams.erase(p.streams.begin() + i);
+                    return;
+                }
+        }
+        if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             aux = nullptr;
         }
     }
-    SideStream(const SideStream&) = delete;
-    SideStream& operator=(const SideStream&) = delete;
     hipEvent_t event() {
         hipEvent_t e = nullptr;
-        SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        {
+            SidePool& p = side_pool();
+            std::lock_guard<std::mutex> lk(p.mu);
+            for (size_t i = 0; i < p.events.size(); ++i)
+                if (p.events[i].first == dev) {
+                    e = p.events[i].second;
+                    p.events.erase(p.events.begin() + i);
+                    break;
+                }
+        }
+        if (!e) SW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         evs.push_back(e);
         return e;
     }
     ~SideStream() {
-        if (aux) (void)hipStreamSynchronize(aux);
-        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-        if (aux) (void)hipStreamDestroy(aux);
+        if (!aux) return;
+        (void)hipStreamSynchronize(aux);
+        SidePool& p = side_pool();
+        std::lock_guard<std::mutex> lk(p.mu);
+        for (hipEvent_t e : evs) p.events.emplace_back(dev, e);
+        p.streams.emplace_back(dev, aux);
     }
 };
 
@@ -1806,6 +1848,81 @@ void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, Sid
 }
 }  // namespace
 
+namespace {
+// The device block of a destroyed preconditioner is kept for the next build of a
+// similar size on the same device: allocating and freeing a few hundred MB costs the host
+// a large share of a set-up, and hipFree waits for the whole device.  At most one block
+// of up to kKeepBytes per device is kept, until the process ends or an allocation fails.
+constexpr size_t kKeepBytes = (size_t)2 << 30;
+struct KeptBlock {
+    int dev;
+    void* p;
+    size_t bytes;
+};
+std::mutex& keep_mu() {
+    static std::mutex* m = new std::mutex();
+    return *m;
+}
+std::vector<KeptBlock>& kept() {
+    static std::vector<KeptBlock>* v = new std::vector<KeptBlock>();
+    return *v;
+}
+
+// A block of at least `bytes` on the current device, or nullptr; *got is its size.
+void* precond_alloc(size_t bytes, size_t* got) {
+    int dev = 0;
+    SW_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(keep_mu());
+        auto& v = kept();
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i].dev == dev && v[i].bytes >= bytes && v[i].bytes <= bytes + bytes / 2) {
+                void* p = v[i].p;
+                *got = v[i].bytes;
+                v.erase(v.begin() + i);
+                return p;
+            }
+    }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(keep_mu());
+            auto& v = kept();
+            for (size_t i = v.size(); i-- > 0;)
+                if (v[i].dev == dev) {
+                    drop.push_back(v[i].p);
+                    v.erase(v.begin() + i);
+                }
+        }
+        for (void* p : drop) (void)hipFree(p);
+        if (drop.empty() || hipMalloc(&mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    *got = bytes;
+    return mem;
+}
+
+// Return a block no kernel uses any more (the caller has synchronised its work).
+void precond_release(void* p, size_t bytes, int dev) {
+    if (!p) return;
+    if (bytes <= kKeepBytes) {
+        std::lock_guard<std::mutex> lk(keep_mu());
+        auto& v = kept();
+        bool have = false;
+        for (const KeptBlock& b : v) have = have || b.dev == dev;
+        if (!have) {
+            v.push_back(KeptBlock{dev, p, bytes});
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+}  // namespace
+
 sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     Geo g = g0;
     g.precision = SW_PREC_FP64;
@@ -1819,9 +1936,8 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->q = q;
     P->nb = nb;
     SW_HIP(hipGetDevice(&P->device));
-    void* mem = nullptr;
-    if (hipMalloc(&mem, bytes) != hipSuccess) {
-        (void)hipGetLastError();
+    void* mem = precond_alloc(bytes, &P->block);
+    if (!mem) {
         delete P;
         throw Error{SW_ENOMEM, "device allocation of the preconditioner failed"};
     }
@@ -1903,7 +2019,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
             if (v != 0) throw Error{SW_ENONFINITE, "preconditioner: singular diagonal block"};
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(P->base);
+        precond_release(P->base, P->block, P->device);
         if (P->terms) (void)hipFree(P->terms);
         if (P->subst) (void)hipGraphExecDestroy(P->subst);
         delete P;
@@ -1995,7 +2111,7 @@ void precond_destroy(sw_precond* P) {
     (void)hipGetDevice(&cur);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(P->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(P->base);
+    precond_release(P->base, P->block, P->device);
     if (P->terms) (void)hipFree(P->terms);
     if (P->subst) (void)hipGraphExecDestroy(P->subst);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(cur);

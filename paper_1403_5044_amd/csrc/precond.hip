@@ -1757,6 +1757,39 @@ SidePool& side_pool() {
     return *p;
 }
 
+}  // namespace
+
+hipStream_t side_stream_take() {
+    int dev = 0;
+    SW_HIP(hipGetDevice(&dev));
+    {
+        SidePool& p = side_pool();
+        std::lock_guard<std::mutex> lk(p.mu);
+        for (size_t i = 0; i < p.streams.size(); ++i)
+            if (p.streams[i].first == dev) {
+                hipStream_t st = p.streams[i].second;
+                p.streams.erase(p.streams.begin() + i);
+                return st;
+            }
+    }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return st;
+}
+
+void side_stream_give(hipStream_t st) {
+    if (!st) return;
+    int dev = 0;
+    SW_HIP(hipGetDevice(&dev));
+    SidePool& p = side_pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.streams.emplace_back(dev, st);
+}
+
+namespace {
 // A helper stream and the events that order it after s.  It goes back to the pool only
 // once s (which waits for the helper at the end) has been synchronised, or after
 // draining both.
@@ -1770,20 +1803,7 @@ struct SideStream {
     void open() {  // without a helper stream the work stays on s
         if (aux) return;
         SW_HIP(hipGetDevice(&dev));
-        {
-            SidePool& p = side_pool();
-            std::lock_guard<std::mutex> lk(p.mu);
-            for (size_t i = 0; i < p.streams.size(); ++i)
-                if (p.streams[i].first == dev) {
-                    aux = p.streams[i].second;
-                    p.streams.erase(p.streams.begin() + i);
-                    return;
-                }
-        }
-        if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
-            (void)hipGetLastError();
-            aux = nullptr;
-        }
+        aux = side_stream_take();
     }
     hipEvent_t event() {
         hipEvent_t e = nullptr;
@@ -1804,10 +1824,12 @@ struct SideStream {
     ~SideStream() {
         if (!aux) return;
         (void)hipStreamSynchronize(aux);
-        SidePool& p = side_pool();
-        std::lock_guard<std::mutex> lk(p.mu);
-        for (hipEvent_t e : evs) p.events.emplace_back(dev, e);
-        p.streams.emplace_back(dev, aux);
+        {
+            SidePool& p = side_pool();
+            std::lock_guard<std::mutex> lk(p.mu);
+            for (hipEvent_t e : evs) p.events.emplace_back(dev, e);
+        }
+        side_stream_give(aux);
     }
 };
 

@@ -378,20 +378,33 @@ int32_t solve_impl(double F, double eps, const sw_mesh* mesh, const sw_domain* d
     try {
         Geo g64 = g;
         g64.precision = SW_PREC_FP64;
-        if (o.precond) {
+        if (o.precond)
             SW_REQUIRE(precond_matches(o.precond, g64),
                        "the preconditioner was built for another mesh or domain");
-        } else {
-            const double tp0 = now_s();
-            own = precond_build(g64, o.q_blocks >= 0 ? o.q_blocks : 1, s);
-            inf.time_precond_s = now_s() - tp0;
-        }
-        SolveTask task(g64, prm, o.precond ? o.precond : own, u, sc.base, pin);
+        SolveTask task(g64, prm, o.precond, u, sc.base, pin);
+        bool need_build = !o.precond;
         while (!task.done()) {
             task.pre(s);
             if (task.done()) break;
             residual_one(*task.req_g, task.req_x, task.req_E, s);
             task.post(s);
+            if (need_build) {
+                // The first step evaluates E(u) only; the preconditioner is built beside it
+                // on a helper stream (it reads nothing of the solve) and is complete when
+                // precond_build returns, before the first Krylov step is enqueued.
+                need_build = false;
+                const double tp0 = now_s();
+                hipStream_t ps = side_stream_take();
+                try {
+                    own = precond_build(g64, o.q_blocks >= 0 ? o.q_blocks : 1, ps ? ps : s);
+                } catch (...) {
+                    side_stream_give(ps);
+                    throw;
+                }
+                side_stream_give(ps);
+                inf.time_precond_s = now_s() - tp0;
+                task.set_precond(own);
+            }
             SW_HIP(hipStreamSynchronize(s));
             task.host(s);
         }

@@ -24,6 +24,10 @@ void precond_destroy(sw_precond* P);
 size_t precond_bytes(const sw_precond* P);
 size_t precond_bytes_estimate(const Geo& g, int q);
 bool precond_matches(const sw_precond* P, const Geo& g);
+// A non-blocking stream of the current device from a pool kept for the process (nullptr
+// if none can be created), and its return once the caller has synchronised its work.
+hipStream_t side_stream_take();
+void side_stream_give(hipStream_t st);
 
 struct SolveParams {
     double tol = 1e-10;
@@ -45,6 +49,8 @@ class SolveTask {
     static size_t pinned_doubles(int m);
 
     bool done() const { return ph_ == Phase::Done; }
+    // the preconditioner may be supplied after construction, before the first Krylov step
+    void set_precond(const sw_precond* P) { P_ = P; }
     void pre(hipStream_t s);
     void post(hipStream_t s);
     void host(hipStream_t s);

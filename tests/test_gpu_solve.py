@@ -195,3 +195,25 @@ def test_preconditioner_band_orders_match_dense_solve(N, M, q):
         log(f"N={N} M={M} q={q} rhs {k}: backward err {res:.2e}")
         assert res <= 1e-12
     P.close()
+
+
+@pytest.mark.parametrize("cfg,q", [(inputs.CONFIG2, 5), (dict(N=241, M=21, x1=-16.0, xN=8.0,
+                                                              yM=12.0, F=0.8, eps=0.2), 8)])
+def test_cold_solve_equals_prebuilt_preconditioner_bitwise(cfg, q):
+    """A cold solve builds its preconditioner on a helper stream beside the first residual
+    evaluation, and the band factorisation runs the super-row operators on another helper
+    stream.  The set-up is deterministic, so the cold solve must equal, bit for bit, the
+    same solve with the preconditioner built beforehand by the public call; a missing
+    ordering between the streams would show up as a difference."""
+    p = gprob(cfg)
+    args = (p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM)
+    u1, z1, i1 = api.solve(*args, q_blocks=q, tol=1e-10)
+    P = api.Preconditioner(p, q)
+    u2, z2, i2 = api.solve(*args, precond=P, tol=1e-10)
+    P.close()
+    u3, z3, i3 = api.solve(*args, q_blocks=q, tol=1e-10)
+    log(f"{p.N}x{p.M} q={q}: cold {i1}, prebuilt {i2}")
+    assert i1.status == 0 and i2.status == 0 and i3.status == 0
+    assert (i1.newton_iters, i1.gmres_iters) == (i2.newton_iters, i2.gmres_iters)
+    assert torch.equal(u1, u2) and torch.equal(z1, z2)
+    assert torch.equal(u1, u3) and torch.equal(z1, z3)

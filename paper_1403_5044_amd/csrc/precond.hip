@@ -1651,9 +1651,22 @@ int elim_step(const Order& o, int l) {
 // S_il in the next step's first launch (the Schur updates read S_il).  Products go to the
 // scratch of their chain and step parity.  The two chains meet only on the separator's
 // own blocks; a bottom update of a block that the top chain updates in the same step
-// goes to a launch of its own.  done(step) runs after each step's launches are enqueued,
-// and done(INT_MAX) after the last.
-void factor_band(sw_precond* P, const Order& o, hipStream_t s,
+// goes to a launch of its own.
+//
+// With a second stream s2 (new_event gives it events), only the Schur updates of the
+// next step's diagonal blocks stay on s: the next inversion needs nothing else, and the
+// other updates and the G copies run on s2 beside it.  s waits for them before the next
+// step's products (which read those blocks and overwrite S_il).  done(step) runs once a
+// step's work is ordered before anything later enqueued on s, and done(INT_MAX) after
+// the last.
+// Blocks wider than this take the second stream: there an inversion (strip launches,
+// about 330 us at N = 241) hides the other updates, and the split paid 17% of the set-up at
+// 241x81; with the register-tile inversion (about 115 us at N = 181) the waits between the
+// streams cost more than the overlap saved.
+constexpr int kSplitSchurN = 192;
+
+void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
+                 const std::function<hipEvent_t()>& new_event,
                  const std::function<void(int)>& done) {
     const Geo& g = P->g;
     const int q = P->q, M = g.M;
@@ -1663,21 +1676,35 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s,
     auto half = [&](int ch, int par) {
         return P->tmp2 + NN * (2 + (size_t)(2 * ch + par) * 2 * q);
     };
-    const int ns = std::max(o.k, o.nB);
-    std::vector<GemmJob> pendingL;
-    for (int step = 0; step < ns + q; ++step) {
-        int rows[2], nr = 0;
+    const int ns = std::max(o.k, o.nB), nsteps = ns + q;
+    auto rows_of = [&](int step, int* rows) {
+        int nr = 0;
         if (step < ns) {
             if (step < o.k) rows[nr++] = step;
             if (step < o.nB) rows[nr++] = M - 1 - step;
-        } else {
+        } else if (step < nsteps) {
             rows[nr++] = o.k + (step - ns);
         }
+        return nr;
+    };
+    std::vector<GemmJob> pendingL;
+    hipEvent_t side_done = nullptr;  // the previous step's work on s2
+    for (int step = 0; step < nsteps; ++step) {
+        int rows[2], next[2];
+        const int nr = rows_of(step, rows);
+        const int nnext = rows_of(step + 1, next);
         // the bottom row's diagonal block is at a higher address than the top row's
         double* d0 = Sb(rows[0], rows[0]);
         const size_t stride = (nr == 2) ? (size_t)(Sb(rows[1], rows[1]) - d0) : 0;
         gj_inverse(g.N, d0, stride, nr, P->info + 2 * step, gjt, P->tmp, s);
-        std::vector<GemmJob> jobs1 = pendingL, jobs2, late;
+        if (side_done) {
+            SW_HIP(hipStreamWaitEvent(s, side_done, 0));
+            side_done = nullptr;
+            done(step - 1);
+        }
+        // wave a: top chain and non-conflicting bottom updates; wave b: bottom updates of
+        // blocks that the top chain updates in this step
+        std::vector<GemmJob> jobs1 = pendingL, diag_a, diag_b, rest_a, rest_b;
         pendingL.clear();
         std::vector<const double*> top_targets;
         for (int e = 0; e < nr; ++e) {
@@ -1699,24 +1726,40 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s,
                 for (int b = 0; b < nn; ++b) {
                     double* Sij = Sb(nbr[a], nbr[b]);
                     const GemmJob j{Sb(nbr[a], l), sc + (size_t)(q + b) * NN, Sij, Sij};
-                    if (ch == 1 && std::find(top_targets.begin(), top_targets.end(), Sij) !=
-                                       top_targets.end())
-                        late.push_back(j);
-                    else
-                        jobs2.push_back(j);
+                    const bool late = ch == 1 && std::find(top_targets.begin(), top_targets.end(),
+                                                           Sij) != top_targets.end();
+                    bool diag = false;
+                    for (int x = 0; x < nnext; ++x) diag = diag || Sij == Sb(next[x], next[x]);
+                    if (!s2) diag = false;  // one stream: everything in the rest launches
+                    (diag ? (late ? diag_b : diag_a) : (late ? rest_b : rest_a)).push_back(j);
                     if (ch == 0) top_targets.push_back(Sij);
                 }
             for (int b = 0; b < nn; ++b)
-                jobs2.push_back(
+                rest_a.push_back(
                     GemmJob{sc + (size_t)(q + b) * NN, nullptr, nullptr, Sb(l, nbr[b])});
             for (int a = 0; a < nn; ++a)
                 pendingL.push_back(GemmJob{sc + (size_t)a * NN, nullptr, nullptr, Sb(nbr[a], l)});
         }
         if (!jobs1.empty()) gemm_batched(g.N, 1.0, jobs1, s);
-        if (!jobs2.empty()) gemm_batched(g.N, -1.0, jobs2, s);
-        if (!late.empty()) gemm_batched(g.N, -1.0, late, s);
-        if (step + 1 < ns + q) done(step);
+        hipStream_t rs = s;
+        if (s2 && (!rest_a.empty() || !rest_b.empty())) {
+            hipEvent_t e = new_event();
+            SW_HIP(hipEventRecord(e, s));
+            SW_HIP(hipStreamWaitEvent(s2, e, 0));
+            rs = s2;
+        }
+        if (!diag_a.empty()) gemm_batched(g.N, -1.0, diag_a, s);
+        if (!diag_b.empty()) gemm_batched(g.N, -1.0, diag_b, s);
+        if (!rest_a.empty()) gemm_batched(g.N, -1.0, rest_a, rs);
+        if (!rest_b.empty()) gemm_batched(g.N, -1.0, rest_b, rs);
+        if (rs != s) {
+            side_done = new_event();
+            SW_HIP(hipEventRecord(side_done, rs));
+        } else if (step + 1 < nsteps) {
+            done(step);
+        }
     }
+    if (side_done) SW_HIP(hipStreamWaitEvent(s, side_done, 0));
     if (!pendingL.empty()) gemm_batched(g.N, 1.0, pendingL, s);
     done(INT_MAX);
 }
@@ -1837,8 +1880,9 @@ struct SideStream {
 // stream as soon as the step that eliminates the stage's last rows is enqueued: the
 // chain of inversions leaves most of the device idle.  s then waits for the helper.
 void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, SideStream& side,
-                       hipStream_t s) {
+                       SideStream& side2, hipStream_t s) {
     side.open();
+    if (P->g.N > kSplitSchurN) side2.open();
     std::vector<int> ready(plan.stages.size(), 0);
     for (size_t k = 0; k < plan.stages.size(); ++k)
         for (int gi : plan.stages[k])
@@ -1848,7 +1892,7 @@ void factor_with_super(sw_precond* P, const Order& o, const SuperPlan& plan, Sid
     std::stable_sort(by_ready.begin(), by_ready.end(),
                      [&](size_t a, size_t b) { return ready[a] < ready[b]; });
     size_t next = 0;
-    factor_band(P, o, s, [&](int step) {
+    factor_band(P, o, s, side2.aux, [&]() { return side2.event(); }, [&](int step) {
         while (next < by_ready.size() && ready[by_ready[next]] <= step) {
             const auto& stage = plan.stages[by_ready[next++]];
             if (!side.aux) continue;  // built on s after the factorisation
@@ -1986,13 +2030,16 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
                       (unsigned)std::min(g.M * nb, 65535));
         k_assemble<<<ag, 256, 0, s>>>(g, q, P->k3, P->Wc, P->S);
         SW_HIP(hipMemsetAsync(P->info, 0, 2 * (size_t)g.M * sizeof(int), s));
-        SideStream side;  // declared before the synchronisation below, released after it
-        if (q == 0)
+        // declared before the synchronisation below, released after it
+        SideStream side, side2;
+        if (q == 0) {
             gj_inverse(g.N, P->S, NN, g.M, P->info, P->tmp2, P->tmp, s);
-        else if (P->sb > 1)
-            factor_with_super(P, order, plan, side, s);
-        else
-            factor_band(P, order, s, [](int) {});
+        } else if (P->sb > 1) {
+            factor_with_super(P, order, plan, side, side2, s);
+        } else {
+            if (g.N > kSplitSchurN) side2.open();
+            factor_band(P, order, s, side2.aux, [&]() { return side2.event(); }, [](int) {});
+        }
         if (q > 0 && P->sb > 1) {
             super_steps(P, plan);
             capture_substitution(P);

@@ -28,10 +28,16 @@
  * example torch tensors), FP64, contiguous.  The library never keeps a caller
  * pointer after the call's stream work has completed.  Library-owned objects
  * (sw_precond, sw_server) are released only by their destroy call.
+ * shipwave_precond_destroy keeps the preconditioner's device block (at most one
+ * block of up to 2 GiB per device) for the next set-up of a similar size; it is
+ * freed when a later device allocation fails, or at process exit.
  *
  * Streams: every call enqueues its work on `stream` and returns without
  * waiting, except shipwave_solve and the server calls, which wait on their own
- * stream for scalar control.  Internal scratch memory is kept per (device,
+ * stream for scalar control, and shipwave_precond_build_banded, which waits for
+ * its set-up to check the diagonal blocks.  Preconditioner set-up also runs
+ * work on library-owned helper streams (a per-device pool, default priority),
+ * ordered with `stream` by events; it is complete when the build call returns.  Internal scratch memory is kept per (device,
  * stream); it grows on demand (hipMalloc, after a stream synchronisation).
  * Calls on one stream are ordered by the stream; calls on different streams
  * use different scratch and may run concurrently.
@@ -124,7 +130,8 @@ int32_t shipwave_jvp(const sw_problem* prob, const double* u, const double* Eu, 
  * |l - m| <= q_blocks kept (block bandwidth b = 2 q_blocks + 1; q_blocks >=
  * M - 1 keeps all of D).  Set-up forms the Schur complement
  * S = D_q - C A^{-1} B and factorises it by block LU (FP64; partial pivoting
- * inside each N x N diagonal block).  P depends on the mesh, domain, F, nu and
+ * inside each N x N diagonal block), eliminating the block rows from both ends
+ * of the band towards q_blocks middle rows, which go last.  P depends on the mesh, domain, F, nu and
  * weights, not on eps or u.  *out receives a library-owned handle. */
 typedef struct sw_precond sw_precond;
 int32_t shipwave_precond_build_banded(const sw_problem* prob, int32_t q_blocks, sw_precond** out,

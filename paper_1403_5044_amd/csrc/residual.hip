@@ -569,17 +569,34 @@ __global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict_
     E[(size_t)g.NM + (size_t)l * g.N + k + 1] = col[(size_t)c * 8 + 6] - s;
 }
 
+// zeta on the grid from the zeta_x half of u: one wavefront per row, the same scan (and
+// summation order) as the zeta half of k_scan, so the result equals the zeta that the
+// residual uses.
 __global__ __launch_bounds__(64) void k_zeta_rows(Geo g, const double* __restrict__ u,
                                                   double* __restrict__ zeta) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= g.M) return;
-    const double* zx = u + g.NM + (size_t)l * g.N;
-    double* out = zeta + (size_t)l * g.N;
-    double v = (-g.x1 / g.nu) * zx[0];
-    out[0] = v;
-    for (int k = 0; k < g.N - 1; ++k) {
-        v += 0.5 * g.dx * (zx[k] + zx[k + 1]);
-        out[k + 1] = v;
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int N = g.N;
+    const double* in = u + g.NM + (size_t)l * N;
+    double* out = zeta + (size_t)l * N;
+    const double hdx = 0.5 * g.dx;
+    const int K = (N + 63) / 64;
+    const int a = min(lane * K, N);
+    const int b = min(a + K, N);
+    double tot = 0.0;
+    for (int m = a; m < b && m < N - 1; ++m) tot += hdx * (in[m] + in[m + 1]);
+    double incl = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    double val = (-g.x1 / g.nu) * in[0] + excl;
+    for (int k = a; k < b; ++k) {
+        out[k] = val;
+        if (k < N - 1) val += hdx * (in[k] + in[k + 1]);
     }
 }
 
@@ -751,7 +768,7 @@ void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, doub
 }
 
 void zeta_enqueue(const Geo& g, const double* u, double* zeta, hipStream_t s) {
-    k_zeta_rows<<<(g.M + 63) / 64, 64, 0, s>>>(g, u, zeta);
+    k_zeta_rows<<<g.M, 64, 0, s>>>(g, u, zeta);
     SW_HIP(hipGetLastError());
 }
 

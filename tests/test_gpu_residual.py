@@ -132,8 +132,12 @@ def test_jvp_matches_oracle_difference_quotient_and_exact_derivative():
     assert np.all(zero == 0.0)
 
 
-def test_zeta_matches_trapezoid_integration():
-    p = gprob(inputs.CONFIG1)
+@pytest.mark.parametrize("cfg", [inputs.CONFIG1, inputs.CONFIG2,
+                                 dict(N=130, M=7, x1=-10.0, xN=8.0, yM=3.0, F=0.8, eps=0.1)])
+def test_zeta_matches_trapezoid_integration(cfg):
+    """One wavefront per row: 31 columns (one point per lane), 181 (three per lane) and
+    130 (three per lane, the last lanes partly or wholly empty)."""
+    p = gprob(cfg)
     u = inputs.smooth_state(p.N, p.M, 0.05, 9)
     z = host(api.zeta(p, dev(u)))
     ref = zeta_grid(oprob(p), u).ravel()

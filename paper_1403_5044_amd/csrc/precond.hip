@@ -21,8 +21,9 @@
 // so that, in elimination order,  forward  y_l = t_l - sum L_{l,c} y_c
 //                  and in reverse, backward x_l = Dinv_l y_l - sum G_{l,c} x_c
 // are block GEMVs.  q = 0 (block bandwidth 1) makes every block independent.
-#include "sw_internal.hpp"
+#include "band_plan.hpp"
 #include "sw_device.hpp"
+#include "sw_internal.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -36,8 +37,6 @@ namespace sw {
 // One step of the super-row substitution: out rows of block row i are
 //   out_i[r] = sum over t in [first[i], first[i+1]) of blk[t][r][:] . vec[t][:]
 // (blk: N x N row-major operator blocks, vec: input blocks of length N).
-constexpr int kMaxSuperRows = 16;
-constexpr int kMaxSuperTerms = 184;
 struct SuperStep {
     int nrow;
     int first[kMaxSuperRows + 1];
@@ -1331,177 +1330,12 @@ size_t gj_work_size(const Geo& g, int q) {
 size_t k3_rows_doubles(const Geo& g) { return (size_t)(2 * g.M - 1) * g.Nc; }
 }  // namespace
 
-// ---- elimination order ----------------------------------------------------------------
-// The band is eliminated from both ends: the top rows [0, k) downwards and the bottom
-// rows [k+q, M) upwards form two chains that share no block (a separator of q rows keeps
-// them more than q apart), so their steps run side by side in the same launches.  The
-// separator rows [k, k+q) go last.  Position p of the order eliminates block row ord[p];
-// the factors are those of block LU of the band with rows and columns in that order.
-struct Order {
-    int k = 0, nB = 0;
-    std::vector<int> ord, rank;  // position -> block row, block row -> position
-};
-
-Order make_order(int M, int q) {
-    Order o;
-    o.k = (M - q + 1) / 2;
-    o.nB = M - q - o.k;
-    for (int l = 0; l < o.k; ++l) o.ord.push_back(l);
-    for (int l = M - 1; l >= o.k + q; --l) o.ord.push_back(l);
-    for (int l = o.k; l < o.k + q; ++l) o.ord.push_back(l);
-    o.rank.assign(M, 0);
-    for (int p = 0; p < M; ++p) o.rank[o.ord[p]] = p;
-    return o;
-}
-
-// ---- super-row substitution -----------------------------------------------------------
-// The block substitutions are regrouped into super rows: runs of b consecutive positions
-// of the elimination order inside one of its three segments.  Forward (L unit lower in
-// that order): the blocks y_R of a super row R satisfy
-//     A_R y_R = t_R - C_R y_ext,   A_R = I + (L inside R),
-// with y_ext the earlier rows that R couples to, so y_R = W_R [y_ext; t_R] with
-// W_R = A_R^{-1} [-C_R | I].  Backward (x_r = Dinv_r y_r - sum G_{r,c} x_c over later c):
-// x_R = W'_R [y_R; x_ext], W'_R = B_R^{-1} [Dg_R | -C'_R], B_R = I + (G inside R).  W and
-// W' are formed once by block substitution on their right-hand sides (GEMMs), keeping
-// only the nonzero blocks.  A top and a bottom super row depend on each other in neither
-// sweep, so each pair runs as one launch.
+// The elimination order and the super-row plan are in band_plan.hpp.
 namespace {
 #ifndef SW_SUPER_TARGET
 #define SW_SUPER_TARGET 1000.0
 #endif
 constexpr double kSuperTarget = SW_SUPER_TARGET;  // b N: super-row height in grid rows
-
-struct SuperRow {
-    std::vector<int> rows;             // block rows in elimination order
-    std::vector<int> ext;              // coupled rows outside R: earlier (fwd) / later (bwd)
-    std::vector<std::vector<int>> id;  // [rows][inputs]: operator block index or -1
-    int terms = 0;
-};
-struct SuperPlan {
-    int b = 0;
-    std::vector<SuperRow> fwd, bwd;          // fwd[i] and bwd[i] cover the same rows
-    std::vector<std::vector<int>> stages;    // super rows launched together, forward order
-    size_t nblocks = 0;
-};
-
-bool coupled(int r, int c, int q) { return r != c && std::abs(r - c) <= q; }
-
-// Nonzero block pattern of W (forward) or W' (backward) of the super row with rows R.
-// Forward inputs are [y_ext..., t_R...]; backward [y_R..., x_ext...].
-SuperRow make_super_row(const Order& o, int q, const std::vector<int>& R, bool fwd,
-                        size_t& next) {
-    SuperRow S;
-    S.rows = R;
-    const int nb = (int)R.size();
-    const int p0 = o.rank[R.front()], p1 = o.rank[R.back()];
-    const int M = (int)o.ord.size();
-    for (int c = 0; c < M; ++c) {
-        const int pc = o.rank[c];
-        if (fwd ? pc >= p0 : pc <= p1) continue;
-        for (int r : R)
-            if (coupled(r, c, q)) {
-                S.ext.push_back(c);
-                break;
-            }
-    }
-    const int ne = (int)S.ext.size(), nin = nb + ne;
-    std::vector<std::vector<char>> nz(nb, std::vector<char>(nin, 0));
-    if (fwd) {
-        for (int i = 0; i < nb; ++i) {
-            for (int c = 0; c < ne; ++c) nz[i][c] = coupled(R[i], S.ext[c], q);
-            nz[i][ne + i] = 1;
-            for (int j = 0; j < i; ++j)
-                if (coupled(R[i], R[j], q))
-                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[j][c];
-        }
-    } else {
-        for (int i = nb - 1; i >= 0; --i) {
-            nz[i][i] = 1;
-            for (int c = 0; c < ne; ++c) nz[i][nb + c] = coupled(R[i], S.ext[c], q);
-            for (int j = i + 1; j < nb; ++j)
-                if (coupled(R[i], R[j], q))
-                    for (int c = 0; c < nin; ++c) nz[i][c] |= nz[j][c];
-        }
-    }
-    S.id.assign(nb, std::vector<int>(nin, -1));
-    for (int i = 0; i < nb; ++i)
-        for (int c = 0; c < nin; ++c)
-            if (nz[i][c]) {
-                S.id[i][c] = (int)next++;
-                ++S.terms;
-            }
-    return S;
-}
-
-// Super rows of b positions per segment (fewer for the separator if its rows do not fit
-// one step); b = 0 if b = 1 would be needed.
-SuperPlan plan_super(const Order& o, int q, int b) {
-    SuperPlan P;
-    if (b <= 1) return P;
-    P.b = b;
-    const int M = (int)o.ord.size();
-    size_t next = 0;
-    auto add = [&](int pa, int pb) {  // positions [pa, pb)
-        std::vector<int> R(o.ord.begin() + pa, o.ord.begin() + pb);
-        P.fwd.push_back(make_super_row(o, q, R, true, next));
-        P.bwd.push_back(make_super_row(o, q, R, false, next));
-        return (int)P.fwd.size() - 1;
-    };
-    std::vector<int> top, bot;
-    for (int p = 0; p < o.k; p += b) top.push_back(add(p, std::min(p + b, o.k)));
-    for (int p = o.k; p < o.k + o.nB; p += b) bot.push_back(add(p, std::min(p + b, o.k + o.nB)));
-    auto fits = [&](const std::vector<int>& st) {
-        int rows = 0, tf = 0, tb = 0;
-        for (int i : st) {
-            rows += (int)P.fwd[i].rows.size();
-            tf += P.fwd[i].terms;
-            tb += P.bwd[i].terms;
-        }
-        return rows <= kMaxSuperRows && std::max(tf, tb) <= kMaxSuperTerms;
-    };
-    for (size_t j = 0; j < std::max(top.size(), bot.size()); ++j) {
-        std::vector<int> st;
-        if (j < top.size()) st.push_back(top[j]);
-        if (j < bot.size()) st.push_back(bot[j]);
-        if (st.size() == 2 && !fits(st)) {
-            P.stages.push_back({st[0]});
-            P.stages.push_back({st[1]});
-        } else {
-            P.stages.push_back(st);
-        }
-    }
-    for (int p = o.k + o.nB; p < M;) {
-        int e = std::min(p + b, M);
-        const size_t mark = next;
-        int i = add(p, e);
-        while (!fits({i}) && e - p > 1) {  // shrink the separator's super row
-            P.fwd.pop_back();
-            P.bwd.pop_back();
-            next = mark;
-            --e;
-            i = add(p, e);
-        }
-        P.stages.push_back({i});
-        p = e;
-    }
-    for (const auto& st : P.stages)
-        if (!fits(st)) return SuperPlan{};
-    P.nblocks = next;
-    return P;
-}
-
-// Super-row height: b N near kSuperTarget grid rows, lowered until every step fits the
-// kernel's argument block; 0 (one block row per step) if no b > 1 fits.
-SuperPlan choose_super(const Geo& g, const Order& o, int q) {
-    if (q == 0) return SuperPlan{};
-    int b = (int)std::lround(kSuperTarget / g.N);
-    b = std::min({b, g.M, kMaxSuperRows});
-    for (; b > 1; --b) {
-        SuperPlan P = plan_super(o, q, b);
-        if (P.b > 1) return P;
-    }
-    return SuperPlan{};
-}
 
 void fill_batched(int N, const std::vector<FillJob>& jobs, hipStream_t s) {
     const size_t NN = (size_t)N * N;
@@ -1634,14 +1468,6 @@ void super_steps(sw_precond* P, const SuperPlan& plan) {
     for (size_t k = plan.stages.size(); k-- > 0;) P->bsteps.push_back(make(plan.stages[k], false));
 }
 
-// Factorisation step that eliminates block row l.
-int elim_step(const Order& o, int l) {
-    const int p = o.rank[l];
-    if (p < o.k) return p;
-    if (p < o.k + o.nB) return p - o.k;
-    return std::max(o.k, o.nB) + (p - o.k - o.nB);
-}
-
 // Block LU of the band in the elimination order of make_order.  Step s < max(k, nB)
 // eliminates top row s and bottom row M-1-s together: one inversion launch for both
 // diagonal blocks, their products in the same GEMM launches.  The separator rows follow
@@ -1769,7 +1595,7 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
     const int q = std::max(0, std::min(q_req, g.M - 1));
     const int nb = 2 * q + 1;
     const size_t N = g.N, NN = N * N, NM = g.NM;
-    const size_t nw = choose_super(g, make_order(g.M, q), q).nblocks;
+    const size_t nw = choose_super(g.N, make_order(g.M, q), q, kSuperTarget).nblocks;
     return carve_size({(size_t)g.M * nb * NN * 8, NN * 8, (size_t)g.ncol * 8, 4 * NM * 8,
                        gj_work_size(g, q) * 8, tmp2_blocks(g, q) * NN * 8, (size_t)g.M * 8,
                        k3_rows_doubles(g) * 8, nw * NN * 8});
@@ -2019,7 +1845,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
     P->info = c.take<int>(2 * (size_t)g.M);
     double* k3rows = c.take<double>(k3_rows_doubles(g));
     const Order order = make_order(g.M, q);
-    const SuperPlan plan = choose_super(g, order, q);
+    const SuperPlan plan = choose_super(g.N, order, q, kSuperTarget);
     P->sb = plan.b;
     P->W = c.take<double>(plan.nblocks * NN);
     try {

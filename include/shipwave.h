@@ -196,7 +196,9 @@ int32_t shipwave_zeta(const sw_problem* prob, const double* u, double* zeta, hip
 int32_t shipwave_profile_enable(int32_t on);
 int32_t shipwave_profile_read(int64_t* launches, double* total_ms, double* pairs);
 
-/* ---- serving: continuous batching of many solves on one GPU ------------ */
+/* ---- serving: continuous batching of many solves on one GPU ------------
+ * Preconditioners are built for F rounded to 0.025 and cached per (mesh, domain,
+ * rounded F, q) while memory allows; the rounding changes only the GMRES count. */
 typedef struct sw_server sw_server;
 typedef struct {
     double hbm_budget_bytes;  /* device memory the server may hold for admitted solves */

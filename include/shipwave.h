@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SHIPWAVE_ABI_VERSION 1
+#define SHIPWAVE_ABI_VERSION 2
 
 enum {
     SW_OK = 0,
@@ -151,7 +151,14 @@ typedef struct {
     int32_t precision;     /* SW_PREC_FP64, or SW_PREC_FP32: FP32-Kahan inner JVPs, FP64 outer */
     int32_t weights;       /* SW_WEIGHTS_* */
     int32_t spline_bc;     /* SW_SPLINE_* */
-    int32_t init;          /* 0: flat surface initial guess; 1: caller's u_inout */
+    int32_t init;          /* initial guess (Jacobian-free Newton-Krylov overview): 0 the flat
+                              surface; 1 the caller's u_inout (eps continuation); 2 the linear
+                              solution u_flat - eps P^{-1} s, s the source term of E2 at the
+                              flat surface, P this solve's preconditioner: the root of the
+                              discretised linear problem when P is the full linear Jacobian
+                              (q_blocks >= M - 1, built for this F), its banded approximation
+                              otherwise.  With init = 2 and no prebuilt preconditioner, P is
+                              built before the first evaluation instead of beside it. */
     double nu;             /* 0 -> 0.05 */
     double eta_max;        /* Eisenstat-Walker forcing cap (default 0.9; <=0 -> default) */
     const sw_precond* precond; /* optional prebuilt preconditioner for this mesh and domain
@@ -166,6 +173,14 @@ typedef struct {
     double final_norm;     /* ||E||_inf in FP64 at the returned u */
     double time_total_s;
     double time_precond_s; /* preconditioner set-up time (0 if supplied) */
+    double fp32_error;     /* max|E32(u) - E64(u)| / max(1, ||E64(u)||_inf) at the returned u,
+                              E32 the FP32-Kahan all-pairs residual and E64 the FP64 one: the
+                              error the FP32 arithmetic carries at the result.  Costs one FP32
+                              evaluation after the solve (not in residual_evals); computed in
+                              both precision modes; -1 if the solve ended on a non-finite
+                              residual. */
+    int32_t linesearch_backtracks; /* halvings of the Newton step length lambda */
+    int32_t reserved;
 } sw_solve_info;
 
 /* Fill opts with the defaults above. */
@@ -196,6 +211,20 @@ int32_t shipwave_zeta(const sw_problem* prob, const double* u, double* zeta, hip
 int32_t shipwave_profile_enable(int32_t on);
 int32_t shipwave_profile_read(int64_t* launches, double* total_ms, double* pairs);
 
+/* Host-forced non-finite residuals, for tests of the failure paths (line-search
+ * backtracking, SW_ENONFINITE, the server's FP64 fallback).  Every solve started after
+ * this call (shipwave_solve and server solves, any thread) writes a NaN into the first
+ * entry of the output of its nth evaluation (1-based, counted per solve and kind) of each
+ * kind in `kinds`, by a one-thread kernel after the residual kernels:
+ *   1  E(u) at the initial state          (-> SW_ENONFINITE)
+ *   2  E at a line-search trial point     (-> lambda halves, the step is retried)
+ *   4  the shifted point of an FP64 JVP   (-> SW_ENONFINITE)
+ *   8  the shifted point of an FP32 JVP   (-> SW_ENONFINITE in mixed precision; a server
+ *                                             with fallback_fp64 then re-solves in FP64)
+ * kinds = 0 or nth = 0 switches it off.  Every kernel runs to completion as usual.
+ * SW_EINVAL for kinds outside [0, 15] or nth < 0. */
+int32_t shipwave_debug_inject_nonfinite(int32_t kinds, int32_t nth);
+
 /* ---- serving: continuous batching of many solves on one GPU ------------
  * Preconditioners are built for F rounded to 0.025 and cached per (mesh, domain,
  * rounded F, q) while memory allows; the rounding changes only the GMRES count. */
@@ -220,6 +249,7 @@ typedef struct {
     int32_t used_fallback;
     double final_norm;
     double t_submit_s, t_admit_s, t_done_s; /* seconds on the server clock */
+    double fp32_error;    /* as sw_solve_info.fp32_error, at the returned u */
 } sw_result;
 
 int32_t shipwave_server_create(const sw_server_opts* opts, sw_server** out);

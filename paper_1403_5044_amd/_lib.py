@@ -39,7 +39,9 @@ class SwSolveOpts(C.Structure):
 class SwSolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("gmres_iters", C.c_int32),
                 ("residual_evals", C.c_int32), ("final_norm", C.c_double),
-                ("time_total_s", C.c_double), ("time_precond_s", C.c_double)]
+                ("time_total_s", C.c_double), ("time_precond_s", C.c_double),
+                ("fp32_error", C.c_double), ("linesearch_backtracks", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SwServerOpts(C.Structure):
@@ -56,7 +58,8 @@ class SwResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("gmres_iters", C.c_int32),
                 ("residual_evals", C.c_int32), ("used_fallback", C.c_int32),
                 ("final_norm", C.c_double), ("t_submit_s", C.c_double),
-                ("t_admit_s", C.c_double), ("t_done_s", C.c_double)]
+                ("t_admit_s", C.c_double), ("t_done_s", C.c_double),
+                ("fp32_error", C.c_double)]
 
 
 P = C.c_void_p
@@ -80,6 +83,7 @@ SIGNATURES = {
     "shipwave_zeta": (I32, [C.POINTER(SwProblem), P, P, P]),
     "shipwave_profile_enable": (I32, [I32]),
     "shipwave_profile_read": (I32, [C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]),
+    "shipwave_debug_inject_nonfinite": (I32, [I32, I32]),
     "shipwave_server_create": (I32, [C.POINTER(SwServerOpts), C.POINTER(P)]),
     "shipwave_server_request_bytes": (I32, [C.POINTER(SwServerOpts), C.POINTER(SwRequest),
                                             C.POINTER(C.c_uint64)]),

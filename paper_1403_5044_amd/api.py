@@ -135,6 +135,13 @@ def profile_read():
     return n.value, ms.value, pr.value
 
 
+def debug_inject_nonfinite(kinds: int, nth: int):
+    """Host-forced NaN in the nth evaluation of each kind in `kinds` (bit 1 initial
+    residual, 2 line-search trial, 4 FP64 JVP point, 8 FP32 JVP point) of every later
+    solve; (0, 0) switches it off.  For tests of the failure paths."""
+    L.check(_lib().shipwave_debug_inject_nonfinite(int(kinds), int(nth)))
+
+
 class Preconditioner:
     """Linear-Jacobian block preconditioner with block half-bandwidth q."""
 
@@ -177,6 +184,8 @@ class SolveInfo:
     final_norm: float
     time_total_s: float
     time_precond_s: float
+    fp32_error: float = -1.0
+    linesearch_backtracks: int = 0
 
 
 def solve_opts(**kw) -> L.SwSolveOpts:
@@ -196,18 +205,26 @@ def solve_opts(**kw) -> L.SwSolveOpts:
     return o
 
 
+INIT = {"flat": 0, "caller": 1, "linear": 2}
+
+
 def solve(F: float, eps: float, N: int, M: int, x1: float, xN: float, yM: float, *,
-          u0=None, want_zeta: bool = True, check: bool = True, **opts):
-    """Newton-Krylov solve of E(u) = 0; returns (u, zeta or None, SolveInfo)."""
+          u0=None, init: str | None = None, want_zeta: bool = True, check: bool = True, **opts):
+    """Newton-Krylov solve of E(u) = 0; returns (u, zeta or None, SolveInfo).
+
+    Initial guess: u0 if given (init "caller"), else init "flat" (default) or "linear"
+    (u_flat - eps P^{-1} s with this solve's preconditioner)."""
     lib = _lib()
     n = 2 * N * M
     o = solve_opts(**opts)
     if u0 is not None:
         u = u0.clone()
-        o.init = 1
+        o.init = INIT["caller"]
     else:
         u = torch.empty(n, dtype=torch.float64, device="cuda")
-        o.init = 0
+        o.init = INIT[init or "flat"]
+        if o.init == INIT["caller"]:
+            raise ValueError("init 'caller' needs u0")
     z = torch.empty(N * M, dtype=torch.float64, device=u.device) if want_zeta else None
     mesh = L.SwMesh(N, M)
     dom = L.SwDomain(x1, xN, yM)
@@ -216,7 +233,8 @@ def solve(F: float, eps: float, N: int, M: int, x1: float, xN: float, yM: float,
                             _dev(u, n, "u"), z.data_ptr() if z is not None else None,
                             C.byref(info), _stream())
     si = SolveInfo(info.status, info.newton_iters, info.gmres_iters, info.residual_evals,
-                   info.final_norm, info.time_total_s, info.time_precond_s)
+                   info.final_norm, info.time_total_s, info.time_precond_s, info.fp32_error,
+                   info.linesearch_backtracks)
     if check and rc not in (0, -4):
         L.check(rc)
     return u, z, si
@@ -234,6 +252,7 @@ class Result:
     t_admit_s: float
     t_done_s: float
     zeta: object = None
+    fp32_error: float = -1.0
 
 
 class Server:
@@ -293,7 +312,7 @@ class Server:
         L.check(rc)
         return Result(res.status, res.newton_iters, res.gmres_iters, res.residual_evals,
                       res.used_fallback, res.final_norm, res.t_submit_s, res.t_admit_s,
-                      res.t_done_s, z)
+                      res.t_done_s, z, res.fp32_error)
 
     def drain(self):
         L.check(self.lib.shipwave_server_drain(self.handle))

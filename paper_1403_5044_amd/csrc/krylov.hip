@@ -253,6 +253,23 @@ __global__ void k_flat(int NM, double* u) {
         u[t] = (t < NM) ? 1.0 : 0.0;
 }
 
+// Source vector of the linear system (linear-problem section): the submerged-source term
+// of E2 at the flat surface, 1 / sqrt(x*^2 + y*^2 + 1) on the E2 rows, zero elsewhere.
+__global__ void k_source(Geo g, double* w) {
+    const int NM = g.NM;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * NM; t += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (t >= NM) {
+            const int l = (t - NM) / g.N, r = (t - NM) - l * g.N;
+            if (r > 0) {
+                const double xs = g.x1 + (r - 0.5) * g.dx, ys = l * g.dy;
+                v = 1.0 / sqrt(xs * xs + ys * ys + 1.0);
+            }
+        }
+        w[t] = v;
+    }
+}
+
 inline int ew_blocks(int n) {
     int b = (n + kThreads - 1) / kThreads;
     return b < 1 ? 1 : (b > 4096 ? 4096 : b);
@@ -312,6 +329,10 @@ void quotient(int n, const double* Ep, const double* Eu, const double* h, double
 }
 
 void flat_state(int NM, double* u, hipStream_t s) { k_flat<<<256, 256, 0, s>>>(NM, u); }
+
+void source_vector(const Geo& g, double* w, hipStream_t s) {
+    k_source<<<ew_blocks(2 * g.NM), kThreads, 0, s>>>(g, w);
+}
 
 void shift_auto(int n, const double* u, const double* z, const double* norms_u, double sqrt_eps,
                 double sqrt_n, double* norms_z, double* h, double* out, double* work,

@@ -44,6 +44,21 @@ struct SuperStep {
     const double* blk[kMaxSuperTerms];
     const double* vec[kMaxSuperTerms];
 };
+
+// One step of the block substitution with one block row per step (super rows of height 1):
+// one or two independent block rows (a top-chain row and the bottom-chain row eliminated in
+// the same factorisation step), out_i = add_i + sum over the row's terms of
+// sign_t blk_t vec_t, the operator blocks read in place from the band factors.
+constexpr int kMaxBandTerms = 64;
+struct BandStep {
+    int nrow;
+    int first[3];
+    const double* add[2];  // t_l (forward) or nullptr (backward)
+    double* out[2];
+    const double* blk[kMaxBandTerms];
+    const double* vec[kMaxBandTerms];
+    double sign[kMaxBandTerms];
+};
 }  // namespace sw
 
 struct sw_precond {
@@ -64,6 +79,7 @@ struct sw_precond {
     int sb = 0;                      // block rows per super row (0: one block row per step)
     double* W = nullptr;             // super-row operators (nonzero N x N blocks)
     std::vector<sw::SuperStep> fsteps, bsteps;  // kernel arguments of the super-row steps
+    std::vector<sw::BandStep> band_steps;       // forward then backward steps when sb <= 1
     std::vector<int> ord;                       // elimination order of the block rows
     size_t bytes = 0;
     size_t block = 0;  // size of the device block at base (>= bytes)
@@ -1209,6 +1225,42 @@ __global__ __launch_bounds__(256) void k_band_step(int N, const GemvTerm* __rest
     if (lane == 0) out[wid] = (add ? add[wid] : 0.0) + s;
 }
 
+// One workgroup per output row of a band step: its kWaves wavefronts take the row's terms
+// in turn, two at a time, so that each lane has several rows of operator blocks in flight;
+// the per-wave dot products are added in a fixed order.
+template <int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void k_band_pair(int N, const BandStep st) {
+    const int row = blockIdx.x;
+    const int i = row / N, r = row - i * N;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t0 = st.first[i], t1 = st.first[i + 1];
+    double s = 0.0;
+    for (int t = t0 + w; t < t1; t += 2 * kWaves) {
+        const bool two = t + kWaves < t1;
+        const double* b0 = st.blk[t] + (size_t)r * N;
+        const double* v0 = st.vec[t];
+        const double* b1 = two ? st.blk[t + kWaves] + (size_t)r * N : b0;
+        const double* v1 = two ? st.vec[t + kWaves] : v0;
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll 4
+        for (int n = lane; n < N; n += 64) {
+            p0 = fma(b0[n], v0[n], p0);
+            p1 = fma(b1[n], v1[n], p1);
+        }
+        s = fma(st.sign[t], p0, s);
+        if (two) s = fma(st.sign[t + kWaves], p1, s);
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    __shared__ double part[kWaves];
+    if (lane == 0) part[w] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = st.add[i] ? st.add[i][r] : 0.0;
+        for (int k = 0; k < kWaves; ++k) sum += part[k];
+        st.out[i][r] = sum;
+    }
+}
+
 // q = 0: x_l = Dinv_l t_l for all l at once (wavefront per output row).
 __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const double* __restrict__ S,
                                                         const double* __restrict__ t,
@@ -1601,7 +1653,7 @@ size_t precond_bytes_estimate(const Geo& g, int q_req) {
                        k3_rows_doubles(g) * 8, nw * NN * 8});
 }
 
-size_t precond_bytes(const sw_precond* P) { return P ? P->bytes : 0; }
+size_t precond_bytes(const sw_precond* P) { return P ? P->block : 0; }
 
 bool precond_matches(const sw_precond* P, const Geo& g) {
     return P && P->g.N == g.N && P->g.M == g.M && P->g.x1 == g.x1 && P->g.xN == g.xN &&
@@ -1610,6 +1662,7 @@ bool precond_matches(const sw_precond* P, const Geo& g) {
 
 namespace {
 void capture_substitution(sw_precond* P);
+void band_steps(sw_precond* P, const Order& o, const std::vector<GemvTerm>& tv);
 }
 
 namespace {
@@ -1903,6 +1956,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
             SW_HIP(hipMalloc(&P->terms, tv.size() * sizeof(GemvTerm)));
             SW_HIP(hipMemcpy(P->terms, tv.data(), tv.size() * sizeof(GemvTerm),
                              hipMemcpyHostToDevice));
+            band_steps(P, order, tv);
             capture_substitution(P);
         }
         SW_HIP(hipGetLastError());
@@ -1924,6 +1978,60 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
 }
 
 namespace {
+// Kernel arguments of the paired band steps (one block row per super row): forward, the
+// top-chain row and the bottom-chain row of each factorisation step together (they share
+// no coupling), then the separator rows one by one; backward in the reverse order.  Left
+// empty (one launch per block row from the device term lists) if a step has more terms
+// than its argument block holds.
+void band_steps(sw_precond* P, const Order& o, const std::vector<GemvTerm>& tv) {
+    const Geo& g = P->g;
+    const size_t NM = g.NM;
+    const int N = g.N;
+    double* t2 = P->work + NM;
+    double* s2 = P->work + 2 * NM;
+    double* tmp = P->work + 3 * NM;
+    std::vector<BandStep> steps;
+    auto add = [&](const std::vector<int>& ps, bool fwd) {
+        BandStep st{};
+        st.nrow = (int)ps.size();
+        int nt = 0;
+        for (int i = 0; i < st.nrow; ++i) {
+            const int p = ps[i], l = o.ord[p];
+            const int off = fwd ? P->fwd_off[p] : P->bwd_off[p];
+            const int cnt = fwd ? P->fwd_cnt[p] : P->bwd_cnt[p];
+            st.first[i] = nt;
+            if (nt + cnt > kMaxBandTerms) return false;
+            for (int t = 0; t < cnt; ++t, ++nt) {
+                st.blk[nt] = tv[off + t].blk;
+                st.vec[nt] = tv[off + t].vec;
+                st.sign[nt] = tv[off + t].sign;
+            }
+            st.add[i] = fwd ? t2 + (size_t)l * N : nullptr;
+            st.out[i] = (fwd ? tmp : s2) + (size_t)l * N;
+        }
+        st.first[st.nrow] = nt;
+        steps.push_back(st);
+        return true;
+    };
+    const int chain = std::max(o.k, o.nB), M = g.M;
+    auto pair = [&](int j) {
+        std::vector<int> ps;
+        if (j < o.k) ps.push_back(j);
+        if (j < o.nB) ps.push_back(o.k + j);
+        return ps;
+    };
+    bool ok = true;
+    for (int j = 0; j < chain && ok; ++j) ok = add(pair(j), true);
+    for (int p = o.k + o.nB; p < M && ok; ++p) ok = add({p}, true);
+    for (int p = M - 1; p >= o.k + o.nB && ok; --p) ok = add({p}, false);
+    for (int j = chain - 1; j >= 0 && ok; --j) ok = add(pair(j), false);
+    if (ok) P->band_steps.swap(steps);
+}
+
+#ifndef SW_BAND_WAVES
+#define SW_BAND_WAVES 4
+#endif
+
 // Block forward and backward substitution with the band factors (q >= 1); all
 // pointers live in the preconditioner, so the sequence can be captured once.
 void enqueue_substitution(const sw_precond* P, hipStream_t s) {
@@ -1940,6 +2048,12 @@ void enqueue_substitution(const sw_precond* P, hipStream_t s) {
             k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st);
         for (const SuperStep& st : P->bsteps)
             k_super_step<<<(unsigned)(st.nrow * N), 256, 0, s>>>(N, st);
+        return;
+    }
+    if (!P->band_steps.empty()) {
+        for (const BandStep& st : P->band_steps)
+            k_band_pair<SW_BAND_WAVES>
+                <<<(unsigned)(st.nrow * N), 64 * SW_BAND_WAVES, 0, s>>>(N, st);
         return;
     }
     const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);
@@ -2000,13 +2114,16 @@ void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t 
     SW_HIP(hipGetLastError());
 }
 
-void precond_destroy(sw_precond* P) {
+void precond_destroy(sw_precond* P, bool keep_block) {
     if (!P) return;
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(P->device);
     (void)hipDeviceSynchronize();
-    precond_release(P->base, P->block, P->device);
+    if (keep_block)
+        precond_release(P->base, P->block, P->device);
+    else
+        (void)hipFree(P->base);
     if (P->terms) (void)hipFree(P->terms);
     if (P->subst) (void)hipGraphExecDestroy(P->subst);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(cur);
@@ -2039,6 +2156,6 @@ int32_t shipwave_precond_apply(const sw_precond* P, const double* b, double* x,
     });
 }
 
-void shipwave_precond_destroy(sw_precond* P) { precond_destroy(P); }
+void shipwave_precond_destroy(sw_precond* P) { precond_destroy(P, true); }
 
 }  // extern "C"

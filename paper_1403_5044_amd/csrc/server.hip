@@ -165,12 +165,15 @@ Geo request_geo(const sw_request& req) {
     return make_geo(p);
 }
 
-// device bytes of one admitted request: its solve state and, unless cached, its
-// preconditioner
+// device bytes of one admitted request, besides its preconditioner: its solve state, its
+// share of the stream's batched-residual scratch (the FP32 layout, the larger one) and
+// its spline operator (kept per M by the residual)
 size_t task_bytes_of(const Geo& g) {
     const int m = SolveParams{}.m;
+    Geo g32 = g;
+    g32.precision = SW_PREC_FP32;
     return carve_size({2 * (size_t)g.NM * 8, (size_t)g.NM * 8}) + SolveTask::device_bytes(g, m) +
-           256;
+           256 + residual_scratch_bytes(g32, choose_chunks(g32)) + (size_t)g.M * g.M * 8;
 }
 }  // namespace
 
@@ -216,7 +219,7 @@ bool sw_server::admit_one(std::unique_lock<std::mutex>& lk) {
                     victim = it;
             if (victim == pcache.end()) return false;  // wait for running solves to finish
             hbm_used -= victim->second.bytes;
-            precond_destroy(victim->second.P);
+            precond_destroy(victim->second.P, false);  // freed: the budget counts it gone
             pcache.erase(victim);
         }
     }
@@ -271,6 +274,7 @@ void sw_server::retire(Active& a, int status) {
     f.res.residual_evals = a.evals;
     f.res.used_fallback = a.used_fallback;
     f.res.final_norm = a.task ? a.task->final_norm : 0.0;
+    f.res.fp32_error = a.task ? a.task->fp32_error : -1.0;
     f.res.t_submit_s = a.t_submit;
     f.res.t_admit_s = a.t_admit;
     f.zeta.assign((size_t)a.g.NM, 0.0);

@@ -10,6 +10,7 @@
 // all-pairs sum on both u + h z and its base point u; the Newton residual, the
 // line search, the closed-form I and the preconditioner stay FP64.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -30,7 +31,16 @@ double now_s() {
 std::mutex g_pin_mu;
 std::multimap<size_t, double*> g_pin_free;
 
+std::atomic<int> g_inject_mask{0}, g_inject_nth{0};
+
+__global__ void k_poison(double* E) { E[0] = __builtin_nan(""); }
+
 }  // namespace
+
+void inject_get(int* mask, int* nth) {
+    *mask = g_inject_mask.load();
+    *nth = g_inject_nth.load();
+}
 
 double* pinned_get(size_t doubles) {
     {
@@ -74,6 +84,9 @@ SolveTask::SolveTask(const Geo& g64, const SolveParams& prm, const sw_precond* P
     : g64_(g64), gin_(g64), prm_(prm), P_(P), u_(u) {
     g64_.precision = SW_PREC_FP64;
     gin_.precision = prm.precision;
+    g32_ = g64;
+    g32_.precision = SW_PREC_FP32;
+    inject_get(&inj_mask_, &inj_nth_);
     n_ = 2 * g64.NM;
     m_ = prm.m;
     const double macheps =
@@ -148,6 +161,11 @@ void SolveTask::pre(hipStream_t s) {
             req_E = Et_;
             req_g = &g64_;
             break;
+        case Phase::Check:
+            req_x = u_;
+            req_E = E32_;
+            req_g = &g32_;
+            break;
         case Phase::Done:
             req_x = nullptr;
             req_E = nullptr;
@@ -156,11 +174,24 @@ void SolveTask::pre(hipStream_t s) {
     }
 }
 
+void SolveTask::maybe_inject(int kind, hipStream_t s) {
+    if (!(inj_mask_ & kind) || inj_nth_ <= 0) return;
+    const int slot = (kind == kInjectNewton) ? 0 : (kind == kInjectLine) ? 1
+                     : (kind == kInjectJvp64) ? 2 : 3;
+    if (++inj_count_[slot] == inj_nth_) k_poison<<<1, 1, 0, s>>>(req_E);
+}
+
 void SolveTask::post(hipStream_t s) {
     const int m = m_;
     switch (ph_) {
         case Phase::E0:
+            maybe_inject(kInjectNewton, s);
+            norm_inf_2(n_, req_E, hd_ + 3 * m + 12, red_, s);
+            SW_HIP(hipMemcpyAsync(pin_out_, hd_ + 3 * m + 12, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            break;
         case Phase::Line:
+            maybe_inject(kInjectLine, s);
             norm_inf_2(n_, req_E, hd_ + 3 * m + 12, red_, s);
             SW_HIP(hipMemcpyAsync(pin_out_, hd_ + 3 * m + 12, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
@@ -168,6 +199,7 @@ void SolveTask::post(hipStream_t s) {
         case Phase::Ein:
             break;
         case Phase::Krylov: {
+            maybe_inject(gin_.precision == SW_PREC_FP32 ? kInjectJvp32 : kInjectJvp64, s);
             double* vn = V_ + (size_t)(j_ + 1) * n_;
             // vn = J z by the difference quotient, then two Gram-Schmidt passes
             cgs_pass(n_, j_ + 1, V_, n_, Ejv_, Ein_, hd_ + 2 * m + 8, vn, hd_, red_, s);
@@ -178,8 +210,16 @@ void SolveTask::post(hipStream_t s) {
             break;
         }
         case Phase::Restart:
+            maybe_inject(gin_.precision == SW_PREC_FP32 ? kInjectJvp32 : kInjectJvp64, s);
             quotient(n_, Ejv_, Ein_, hd_ + 2 * m + 8, w_, s);
             axpby(n_, -1.0, E_, -1.0, w_, w_, s);
+            norm_inf_2(n_, w_, hd_ + 3 * m + 12, red_, s);
+            SW_HIP(hipMemcpyAsync(pin_out_, hd_ + 3 * m + 12, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            break;
+        case Phase::Check:
+            // E_ holds E64 at the returned u
+            axpby(n_, 1.0, E32_, -1.0, E_, w_, s);
             norm_inf_2(n_, w_, hd_ + 3 * m + 12, red_, s);
             SW_HIP(hipMemcpyAsync(pin_out_, hd_ + 3 * m + 12, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
@@ -192,7 +232,10 @@ void SolveTask::post(hipStream_t s) {
 void SolveTask::finish(int st) {
     status = st;
     final_norm = nr_[0];
-    ph_ = Phase::Done;
+    // u_ is the returned iterate and E_ = E64(u_) in every case that reaches here with a
+    // finite norm (the initial state, an accepted step, or a rejected line search that
+    // left u_ and E_ unchanged): one FP32 evaluation at u_ measures the FP32 error there
+    ph_ = (std::isfinite(nr_[0]) && std::isfinite(nr_[1])) ? Phase::Check : Phase::Done;
 }
 
 void SolveTask::newton_top(hipStream_t s) {
@@ -253,6 +296,12 @@ void SolveTask::finish_cycle(hipStream_t s, bool converged) {
 void SolveTask::host(hipStream_t s) {
     const int m = m_;
     if (ph_ == Phase::Done) return;
+    if (ph_ == Phase::Check) {
+        fp32_error = pin_out_[0] / std::max(1.0, nr_[0]);
+        if (!std::isfinite(fp32_error)) fp32_error = -1.0;
+        ph_ = Phase::Done;
+        return;
+    }
     ++evals;
     switch (ph_) {
         case Phase::E0:
@@ -327,6 +376,7 @@ void SolveTask::host(hipStream_t s) {
                 newton_top(s);
             } else {
                 lam_ *= 0.5;
+                ++backtracks;
                 if (lam_ < 1e-4) return finish(SW_ENOCONV);
             }
             break;
@@ -349,7 +399,7 @@ int32_t solve_impl(double F, double eps, const sw_mesh* mesh, const sw_domain* d
     SW_REQUIRE(o.max_newton >= 1 && o.gmres_restart >= 1 && o.max_gmres >= 1,
                "iteration limits must be >= 1");
     SW_REQUIRE(o.gmres_restart <= 200, "gmres_restart must be <= 200");
-    SW_REQUIRE(o.init == 0 || o.init == 1, "init must be 0 or 1");
+    SW_REQUIRE(o.init >= 0 && o.init <= 2, "init must be 0, 1 or 2");
     sw_problem p{};
     p.mesh = *mesh;
     p.domain = *dom;
@@ -381,8 +431,28 @@ int32_t solve_impl(double F, double eps, const sw_mesh* mesh, const sw_domain* d
         if (o.precond)
             SW_REQUIRE(precond_matches(o.precond, g64),
                        "the preconditioner was built for another mesh or domain");
-        SolveTask task(g64, prm, o.precond, u, sc.base, pin);
         bool need_build = !o.precond;
+        const sw_precond* P0 = o.precond;
+        if (o.init == 2) {
+            // Linear-solution initial guess u = u_flat - eps P^{-1} s: the root of the
+            // linear system when P is the full linear Jacobian (q >= M - 1, built for this F).
+            // P is needed before the first evaluation, so it is built here, on `s`.
+            if (need_build) {
+                const double tp0 = now_s();
+                own = precond_build(g64, o.q_blocks >= 0 ? o.q_blocks : 1, s);
+                inf.time_precond_s = now_s() - tp0;
+                P0 = own;
+                need_build = false;
+            }
+            const size_t n = 2 * (size_t)g64.NM;
+            double* w = static_cast<double*>(sc.base);  // the task's memory, not yet in use
+            double* z = w + n;
+            flat_state(g64.NM, u, s);
+            source_vector(g64, w, s);
+            precond_apply(P0, w, z, s);
+            axpby((int)n, 1.0, u, -eps, z, u, s);
+        }
+        SolveTask task(g64, prm, P0, u, sc.base, pin);
         while (!task.done()) {
             task.pre(s);
             if (task.done()) break;
@@ -415,6 +485,8 @@ int32_t solve_impl(double F, double eps, const sw_mesh* mesh, const sw_domain* d
         inf.gmres_iters = task.gmres_total;
         inf.residual_evals = task.evals;
         inf.final_norm = task.final_norm;
+        inf.fp32_error = task.fp32_error;
+        inf.linesearch_backtracks = task.backtracks;
     } catch (...) {
         (void)hipStreamSynchronize(s);
         if (own) precond_destroy(own);
@@ -449,6 +521,15 @@ void shipwave_solve_opts_default(sw_solve_opts* o) {
     o->nu = 0.05;
     o->eta_max = 0.9;
     o->precond = nullptr;
+}
+
+int32_t shipwave_debug_inject_nonfinite(int32_t kinds, int32_t nth) {
+    return guard([&]() -> int32_t {
+        SW_REQUIRE(kinds >= 0 && kinds <= 15 && nth >= 0, "kinds must be in [0, 15], nth >= 0");
+        sw::g_inject_nth.store(kinds ? nth : 0);
+        sw::g_inject_mask.store(nth ? kinds : 0);
+        return SW_OK;
+    });
 }
 
 int32_t shipwave_solve(double F, double eps, const sw_mesh* mesh, const sw_domain* domain,

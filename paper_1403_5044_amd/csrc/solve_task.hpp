@@ -20,8 +20,10 @@ namespace sw {
 
 sw_precond* precond_build(const Geo& g, int q, hipStream_t s);
 void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t s);
-void precond_destroy(sw_precond* P);
-size_t precond_bytes(const sw_precond* P);
+// keep_block: the device block may be kept for the next set-up of a similar size
+// (otherwise it is freed at once)
+void precond_destroy(sw_precond* P, bool keep_block = true);
+size_t precond_bytes(const sw_precond* P);  // device bytes the preconditioner holds
 size_t precond_bytes_estimate(const Geo& g, int q);
 bool precond_matches(const sw_precond* P, const Geo& g);
 // A non-blocking stream of the current device from a pool kept for the process (nullptr
@@ -38,6 +40,17 @@ struct SolveParams {
     double eta_max = 0.9;
     bool init_flat = true;
 };
+
+// Host-forced non-finite residuals for tests of the failure paths: the nth evaluation
+// (1-based, counted per task) of each kind in the mask gets a NaN written into the first
+// entry of its output by a one-thread kernel, after the residual kernels have finished.
+enum : int {
+    kInjectNewton = 1,  // E(u) at the initial state
+    kInjectLine = 2,    // E at a line-search trial point
+    kInjectJvp64 = 4,   // shifted-point evaluation of an FP64 JVP
+    kInjectJvp32 = 8    // shifted-point evaluation of an FP32 JVP (mixed precision)
+};
+void inject_get(int* mask, int* nth);
 
 class SolveTask {
    public:
@@ -62,19 +75,26 @@ class SolveTask {
     int status = SW_ENOCONV;
     int newton = 0;
     int gmres_total = 0;
-    int evals = 0;
+    int evals = 0;         // evaluations of the solve (the closing FP32 check not included)
+    int backtracks = 0;    // line-search halvings of lambda
     double final_norm = 0.0;
+    // max |E32(u) - E64(u)| / max(1, ||E64(u)||_inf) at the returned u (one FP32-Kahan
+    // evaluation after the solve ends); -1 when the solve ended on a non-finite value
+    double fp32_error = -1.0;
     double* u() const { return u_; }
     const Geo& geo() const { return g64_; }
 
    private:
-    enum class Phase { E0, Ein, Krylov, Restart, Line, Done };
+    enum class Phase { E0, Ein, Krylov, Restart, Line, Check, Done };
     void newton_top(hipStream_t s);
     void start_gmres(hipStream_t s);
     void finish_cycle(hipStream_t s, bool converged);
     void finish(int st);
+    void maybe_inject(int kind, hipStream_t s);
 
-    Geo g64_, gin_;
+    Geo g64_, gin_, g32_;
+    int inj_mask_ = 0, inj_nth_ = 0;
+    int inj_count_[4] = {0, 0, 0, 0};
     SolveParams prm_;
     const sw_precond* P_;
     int n_, m_;

@@ -145,6 +145,8 @@ void shift(int n, const double* u, const double* z, const double* h, double* out
 void quotient(int n, const double* Ep, const double* Eu, const double* h, double* out,
               hipStream_t s);
 void flat_state(int NM, double* u, hipStream_t s);  // phi_x = 1, zeta_x = 0
+// w = s, the source term of E2 at the flat surface per unit eps (linear system's right side)
+void source_vector(const Geo& g, double* w, hipStream_t s);
 // norm_inf_2(z) into norms_z, jvp_step(norms_u, norms_z) into h and shift(u, z, h) into
 // out, in two launches (work as for norm_inf_2).
 void shift_auto(int n, const double* u, const double* z, const double* norms_u, double sqrt_eps,

@@ -1,4 +1,5 @@
-"""Writes the stored inputs under tests/golden/ by calling only the oracle.
+"""Writes the stored inputs and expected values under tests/golden/ by calling
+only the oracle.
 
 config2_linear_state.npy: the root of the discrete linear system (the
 linearised problem of the paper's linear-problem section, discretised as in
@@ -7,7 +8,16 @@ F = 0.7, i.e. u_flat - eps J_lin^{-1} s, solved through the Schur complement
 of Appendix C with all of D kept.  It seeds the residual-throughput batch
 (linear solution plus N(0, 1e-3^2) noise).
 
-Run:  python tests/golden/make_golden.py
+config2_root.npy: the root of the nonlinear system E(u) = 0 on the same mesh
+and parameters, by the oracle's damped Newton (exact complex-step JVPs, GMRES
+preconditioned by the full linear Jacobian) to ||E||_inf <= 1e-12, started
+from the linear solution (the eps-continuation path from the flat surface:
+the linear solution is the first-order term of that path).  The converged
+surface heights zeta are compared with the GPU solve.
+
+Each file is stored with its SHA-256.
+
+Run:  python tests/golden/make_golden.py [linear] [root]
 """
 import hashlib
 import os
@@ -20,20 +30,46 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import Problem  # noqa: E402
-from oracle.linear import linear_solution  # noqa: E402
+from oracle.linear import BlockPreconditioner, linear_solution  # noqa: E402
+from oracle.solve import newton  # noqa: E402
 
 
-def main():
-    t = time.time()
-    prob = Problem(181, 61, -16.0, 8.0, 12.0, F=0.7, eps=0.1)
-    u = linear_solution(prob)
-    path = os.path.join(HERE, "config2_linear_state.npy")
-    np.save(path, u, allow_pickle=False)
+def _store(name, arr):
+    path = os.path.join(HERE, name)
+    np.save(path, arr, allow_pickle=False)
     digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
     with open(path + ".sha256", "w") as f:
-        f.write(f"{digest}  config2_linear_state.npy\n")
+        f.write(f"{digest}  {name}\n")
+    return path, digest
+
+
+def config2():
+    return Problem(181, 61, -16.0, 8.0, 12.0, F=0.7, eps=0.1)
+
+
+def make_linear():
+    t = time.time()
+    u = linear_solution(config2())
+    path, digest = _store("config2_linear_state.npy", u)
     print(f"wrote {path} ({u.size} values) in {time.time() - t:.1f} s, sha256 {digest}")
 
 
+def make_root():
+    t = time.time()
+    prob = config2()
+    pre = BlockPreconditioner(prob, prob.M - 1)
+    u0 = linear_solution(prob, pre)
+    u, info = newton(prob, u0, tol=1e-12, pre=pre, eta=1e-6)
+    if not info.converged:
+        raise RuntimeError(f"oracle Newton did not converge: {info}")
+    path, digest = _store("config2_root.npy", u)
+    print(f"wrote {path} in {time.time() - t:.1f} s: {info.newton} Newton, {info.gmres} GMRES, "
+          f"norms {['%.2e' % v for v in info.norms]}, sha256 {digest}")
+
+
 if __name__ == "__main__":
-    main()
+    which = sys.argv[1:] or ["linear", "root"]
+    if "linear" in which:
+        make_linear()
+    if "root" in which:
+        make_root()

@@ -34,7 +34,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     lib = _lib.load()
-    assert lib.shipwave_abi_version() == 1
+    assert lib.shipwave_abi_version() == 2
     assert isinstance(lib.shipwave_last_error(), bytes)
 
 
@@ -42,6 +42,17 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.SwProblem) == 8 + 24 + 40
     assert ctypes.sizeof(_lib.SwParams) == 40
     assert ctypes.sizeof(_lib.SwSolveOpts) == 8 + 8 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.SwSolveInfo) == 4 * 4 + 4 * 8 + 2 * 4
+    assert _lib.SwSolveInfo.fp32_error.offset == 40
+    assert ctypes.sizeof(_lib.SwResult) == 5 * 4 + 4 + 5 * 8
+    assert _lib.SwResult.fp32_error.offset == 56
+
+
+def test_fault_injection_rejects_bad_arguments_on_the_host():
+    lib = _lib.load()
+    assert lib.shipwave_debug_inject_nonfinite(16, 1) == -1
+    assert lib.shipwave_debug_inject_nonfinite(1, -1) == -1
+    assert lib.shipwave_debug_inject_nonfinite(0, 0) == 0
 
 
 def test_request_footprint_query_is_host_only_and_monotone():

@@ -1,0 +1,129 @@
+"""Parity at the full shapes of configs 2-4 (181x61, 361x121 and 721x241), through the
+C ABI, against the FP64 oracle.
+
+  * config 2: one state on every entry of E; the converged surface against the oracle's
+    own root (stored by tests/golden/make_golden.py with its SHA-256);
+  * configs 3 and 4: every E1/E4/E6 entry and 96 E2 entries (each a full sum over the
+    grid) -- these meshes take the pair kernel's many-tile chunking;
+  * the FP32-Kahan residual against the FP64 oracle on the same rows, against the bound
+    stated below;
+  * a mesh with M > 512 rows, where the y-spline runs as per-column tridiagonal sweeps
+    instead of the cached dense slope operator.
+
+FP64 gate: |E_gpu - E_oracle| <= 1e-11 * scale per entry, scale = the sum of |terms| of
+that entry, floored at 1 (as for the small meshes).
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from oracle.equations import residual_rows, row_scale, zeta_grid
+from oracle import residual as oresidual
+from paper_1403_5044_amd import api, inputs
+
+from gpu_common import dev, gprob, gpu_residual, host, log, oprob
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+# FP32-Kahan bound.  Each pair term takes about 20 FP32 operations on inputs rounded to
+# FP32 (one rounding each, u = 2^-24), and the Kahan-compensated row sums add at most
+# 2u of the summed magnitudes; 32u = 2^-19 of the scale bounds the error of the sum to
+# first order.
+TOL32 = 2.0 ** -19
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rows(p, n_e2, seed):
+    """Every E1/E4/E6 entry, the E2 corners of the collocation grid and n_e2 random E2
+    entries."""
+    NM = p.N * p.M
+    rng = np.random.default_rng(seed)
+    e2 = NM + rng.integers(0, p.M, n_e2) * p.N + rng.integers(1, p.N, n_e2)
+    corners = [NM + 1, NM + p.N - 1, NM + (p.M - 1) * p.N + 1, 2 * NM - 1]
+    return np.unique(np.concatenate([np.arange(NM), np.arange(NM, 2 * NM, p.N), e2, corners]))
+
+
+def test_config2_every_entry_fp64():
+    p = gprob(inputs.CONFIG2)
+    u = inputs.config2_batch(3)[2]
+    E = gpu_residual(p, u)
+    op = oprob(p)
+    Eo = oresidual(op, u)
+    err = np.abs(E - Eo) / row_scale(op, u)
+    log(f"config2 all {E.size} entries: max rel err {err.max():.3e}")
+    assert err.max() <= TOL64
+
+
+@pytest.mark.parametrize("name,cfg,amp", [("config3", inputs.CONFIG3, 0.02),
+                                          ("config4", inputs.CONFIG4, 0.02)])
+def test_large_mesh_residual_fp64_and_fp32(name, cfg, amp):
+    p = gprob(cfg)
+    op = oprob(p)
+    u = inputs.smooth_state(p.N, p.M, amp, 11)
+    rows = _rows(p, 96, 5)
+    Eo, sc = residual_rows(op, u, rows)
+    E64 = gpu_residual(p, u)[rows]
+    E32 = gpu_residual(p.with_(precision="fp32"), u)[rows]
+    e64 = (np.abs(E64 - Eo) / sc).max()
+    e32 = (np.abs(E32 - Eo) / sc).max()
+    log(f"{name}: {rows.size} rows; FP64 max rel err {e64:.3e}; FP32-Kahan {e32:.3e} "
+        f"(bound {TOL32:.2e})")
+    assert e64 <= TOL64
+    assert e32 <= TOL32
+
+
+def test_config2_fp32_error_against_the_oracle():
+    p = gprob(inputs.CONFIG2)
+    op = oprob(p)
+    worst = 0.0
+    for s, u in enumerate(inputs.config2_batch(4)):
+        rows = _rows(p, 48, 100 + s)
+        Eo, sc = residual_rows(op, u, rows)
+        E32 = gpu_residual(p.with_(precision="fp32"), u)[rows]
+        worst = max(worst, (np.abs(E32 - Eo) / sc).max())
+    log(f"config2: FP32-Kahan max rel err vs oracle {worst:.3e} (bound {TOL32:.2e})")
+    assert worst <= TOL32
+
+
+@pytest.mark.parametrize("N,M", [(5, 521), (9, 600)])
+def test_tall_mesh_spline_sweeps(N, M):
+    """M > 512: the spline slopes come from a tridiagonal sweep per column."""
+    p = api.Problem(N, M, -3.0, 3.0, 40.0, F=0.7, eps=0.2)
+    for k, u in enumerate([inputs.smooth_state(N, M, 0.05, 3),
+                           inputs.perturbed(inputs.flat_state(N, M), 1e-3, 4)]):
+        E = gpu_residual(p, u)
+        op = oprob(p)
+        err = (np.abs(E - oresidual(op, u)) / row_scale(op, u)).max()
+        log(f"{N}x{M} state {k}: max rel err {err:.3e}")
+        assert err <= TOL64
+
+
+def _golden_root():
+    path = os.path.join(GOLDEN, "config2_root.npy")
+    want = open(path + ".sha256").read().split()[0]
+    assert hashlib.sha256(open(path, "rb").read()).hexdigest() == want
+    return np.load(path, allow_pickle=False)
+
+
+def test_config2_zeta_matches_the_oracle_root():
+    """The FP64 GPU solve of config 2 to ||E||_inf <= 1e-12 against the oracle's root
+    (converged to the same tolerance): zeta element by element within 1e-8; the mixed-
+    precision solve within the stated 1e-6."""
+    p = gprob(inputs.CONFIG2)
+    uo = _golden_root()
+    zo = zeta_grid(oprob(p), uo).ravel()
+    u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, tol=1e-12, max_newton=20)
+    log(f"config2 fp64 tol 1e-12: {info}")
+    assert info.status == 0
+    dz = np.abs(host(z) - zo).max()
+    du = np.abs(host(u) - uo).max()
+    log(f"config2 zeta vs oracle root {dz:.2e}; u {du:.2e}")
+    assert dz <= 1e-8
+    um, zm, im = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
+                           tol=1e-10)
+    dzm = np.abs(host(zm) - zo).max()
+    log(f"config2 mixed: {im}; zeta vs oracle root {dzm:.2e}")
+    assert im.status == 0 and dzm <= 1e-6

@@ -158,12 +158,15 @@ def test_preconditioner_graph_replays_match_the_dense_solve():
 
 
 @pytest.mark.parametrize("N,M", [(64, 6), (65, 7), (121, 9), (181, 7), (182, 5), (183, 5),
-                                 (192, 5), (241, 5), (256, 4), (257, 4), (521, 4)])
+                                 (192, 5), (241, 5), (256, 4), (257, 4), (521, 4), (667, 4),
+                                 (721, 4), (1024, 4)])
 def test_preconditioner_wide_blocks_match_dense_solve(N, M):
     """Every diagonal-block inversion variant against the oracle's dense P: the
     register-tile kernel with 1, 2 and 3 panel rows per lane (13- and 14-row tiles on
     either side of N = 182), the column-strip launches up to N = 256, and beyond that
-    the panel and update launches with 2 and 4 panel rows per thread."""
+    the panel and update launches with 2 and 4 panel rows per thread.  From N = 667 the
+    substitution runs one block row per step (no super rows), the path of 721 x 241;
+    N = 1024 is the largest mesh width the library accepts."""
     p = api.Problem(N, M, -10.0, 8.0, 3.0, F=0.75, eps=0.1)
     op = oprob(p)
     b = np.random.default_rng(N).standard_normal(p.n_unknowns)

@@ -115,6 +115,19 @@ int32_t shipwave_residual(const sw_problem* prob, const double* u, double* E, hi
 int32_t shipwave_residual_batched(int32_t nb, const sw_problem* probs, const double* const* u,
                                   double* const* E, hipStream_t stream);
 
+/* E(u) as shipwave_residual, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * intermediate arrays live in a fixed device array of 64 MiB inside the library, one per
+ * GPU, held from the first call on that GPU until the process ends; the call allocates
+ * nothing and creates no runtime object.  The spline slopes come from a tridiagonal sweep
+ * per column instead of the cached dense operator, so results equal shipwave_residual's
+ * to rounding (not bitwise).  Meshes whose arrays exceed 64 MiB return SW_ENOMEM (721 x
+ * 241 needs 43 MiB in FP64, 48 MiB in FP32).  Every call on one GPU uses the same array:
+ * calls that overlap on one GPU (other streams, other threads) race and must be ordered
+ * by the caller; calls on one stream are ordered by it.  u, E: as shipwave_residual. */
+int32_t shipwave_residual_noalloc(const sw_problem* prob, const double* u, double* E,
+                                  hipStream_t stream);
+
 /* Jacobian-vector product by a first-order difference quotient (eq. JvApprox):
  * Jz = (E(u + h z) - Eu) / h.  Eu must be E(u) computed with the same
  * precision setting.  h <= 0 selects h = sqrt(macheps) (sqrt(n) + ||u||_2) / ||z||_2,

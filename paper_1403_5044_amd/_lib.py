@@ -73,6 +73,7 @@ SIGNATURES = {
     "shipwave_residual": (I32, [C.POINTER(SwProblem), P, P, P]),
     "shipwave_residual_batched": (I32, [I32, C.POINTER(SwProblem), C.POINTER(P), C.POINTER(P),
                                         P]),
+    "shipwave_residual_noalloc": (I32, [C.POINTER(SwProblem), P, P, P]),
     "shipwave_jvp": (I32, [C.POINTER(SwProblem), P, P, P, D, P, P]),
     "shipwave_precond_build_banded": (I32, [C.POINTER(SwProblem), I32, C.POINTER(P), P]),
     "shipwave_precond_apply": (I32, [P, P, P, P]),

@@ -84,6 +84,16 @@ def residual(prob: Problem, u: torch.Tensor, out: torch.Tensor | None = None) ->
     return out
 
 
+def residual_noalloc(prob: Problem, u: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """E(u) through the entry point that allocates nothing (the library's fixed array)."""
+    lib = _lib()
+    n = prob.n_unknowns
+    ps = prob.c_struct()
+    L.check(lib.shipwave_residual_noalloc(C.byref(ps), _dev(u, n, "u"), _dev(out, n, "E"),
+                                          _stream()))
+    return out
+
+
 def residual_batched(probs, us, outs=None):
     """E(u_b) for several problems in shared launches."""
     lib = _lib()

@@ -672,7 +672,8 @@ ResidualBufs carve_residual(Carve& c, const Geo& g, int G) {
 }
 
 namespace {
-void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s);
+void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s,
+             bool dense_spline = true);
 }
 
 void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBufs& b,
@@ -693,10 +694,30 @@ void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBu
     SW_HIP(hipGetLastError());
 }
 
+void residual_enqueue_fixed(const Geo& g, const double* u, double* E, const ResidualBufs& b,
+                            hipStream_t s) {
+    // the same kernels as residual_enqueue, except that the spline slopes come from the
+    // per-column sweep (its coefficients live in b.spl), not the cached dense operator,
+    // and the launches are not timed: nothing is allocated or created
+    prelude(g, u, E, b, s, false);
+    if (g.precision == SW_PREC_FP32) {
+        const int ntiles = (g.ncol + kPairThreads * kCP32 - 1) / (kPairThreads * kCP32);
+        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)g.N * 32, s>>>(
+            g, b.src32, b.col, b.partial, ntiles, b.G);
+    } else {
+        const int ntiles = (g.ncol + kPairThreads * kCP64 - 1) / (kPairThreads * kCP64);
+        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)g.N * 64, s>>>(
+            g, b.src64, b.col, b.partial, ntiles, b.G);
+    }
+    k_finish<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, b.col, b.partial, b.G, E);
+    SW_HIP(hipGetLastError());
+}
+
 namespace {
-void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s) {
+void prelude(const Geo& g, const double* u, double* E, const ResidualBufs& b, hipStream_t s,
+             bool dense_spline) {
     k_scan<<<dim3(g.M, 2), 64, 0, s>>>(g, u, b.psi, b.zeta, E);
-    if (const double* Q = spline_operator(g.M, g.bc, s)) {
+    if (const double* Q = dense_spline ? spline_operator(g.M, g.bc, s) : nullptr) {
         k_spline_dense<<<dim3((g.N + 127) / 128, g.M, 2), 128, 0, s>>>(g, Q, b.psi, b.zeta,
                                                                        b.psiy, b.zetay);
     } else {

@@ -119,6 +119,10 @@ int choose_chunks(const Geo& g);
 // Enqueue E(u) for one problem on `stream` using bufs (already carved).
 void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBufs& b,
                       hipStream_t stream);
+// The same residual with nothing allocated or created on the way (for the entry point
+// that takes no memory of its own): spline slopes by the per-column sweep, no timing.
+void residual_enqueue_fixed(const Geo& g, const double* u, double* E, const ResidualBufs& b,
+                            hipStream_t stream);
 // Batched form: shared launches over nb problems.
 void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, double* const* E,
                               hipStream_t stream);

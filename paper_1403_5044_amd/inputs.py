@@ -9,6 +9,7 @@ the shapes this suite is modelled on):
   config2  181 x 61  x in [-16, 8],  y in [0, 12],  eps 0.1,  F 0.7
   config3  361 x 121 x in [-14, 40], y in [0, 18],  F in {0.5, 0.7, 1.0}, eps in {0.1, 0.3}
   config4  721 x 241 x in [-14, 40], y in [0, 18],  F 0.7, eps 0.1 .. 0.5
+  F = 1.4  721 x 241 x in [-56, 160], y in [0, 72],  eps 1 (spacing 0.3)
   serving  meshes {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
            F ~ U[0.5, 1.0], eps ~ U[0.05, 0.4], Poisson arrivals
 """
@@ -29,6 +30,10 @@ CONFIG3_F = (0.5, 0.7, 1.0)
 CONFIG3_EPS = (0.1, 0.3)
 CONFIG4 = dict(N=721, M=241, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
 CONFIG4_EPS = (0.1, 0.2, 0.3, 0.4, 0.5)
+# F = 1.4 on 721 x 241 with spacing 0.3 from x_1 = -56 (the paper's F = 1.4 surface)
+CONFIG_F14 = dict(N=721, M=241, x1=-56.0, xN=160.0, yM=72.0, F=1.4, eps=1.0)
+# Solver settings of the large-mesh solves (361 x 121 and beyond)
+LARGE_SOLVE = dict(tol=1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
 SERVING_MESHES = ((61, 21), (121, 41), (181, 61), (241, 81))
 SERVING_DOMAIN = dict(x1=-16.0, xN=8.0, yM=12.0)
 # Table 1 meshes (every row at eps = 1, F = 0.7); spacing 0.3 (91 x 31, x_1 = -9)

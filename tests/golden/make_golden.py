@@ -15,9 +15,16 @@ from the linear solution (the eps-continuation path from the flat surface:
 the linear solution is the first-order term of that path).  The converged
 surface heights zeta are compared with the GPU solve.
 
+table1_91x31_eps1_root.npy: the root at eps = 1, F = 0.7 on the 91 x 31 mesh of
+the paper's results section (spacing 0.3, x_1 = -9, so x in [-9, 18] and
+y in [0, 9]), reached by eps continuation in steps of 0.1 from the flat
+surface (each root starts the next Newton solve; the bootstrapping paragraph
+of the JFNK overview), every step to ||E||_inf <= 1e-12 with the full linear
+Jacobian as preconditioner.
+
 Each file is stored with its SHA-256.
 
-Run:  python tests/golden/make_golden.py [linear] [root]
+Run:  python tests/golden/make_golden.py [linear] [root] [table1]
 """
 import hashlib
 import os
@@ -31,7 +38,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import Problem  # noqa: E402
 from oracle.linear import BlockPreconditioner, linear_solution  # noqa: E402
-from oracle.solve import newton  # noqa: E402
+from oracle.solve import continuation, newton  # noqa: E402
 
 
 def _store(name, arr):
@@ -67,9 +74,26 @@ def make_root():
           f"norms {['%.2e' % v for v in info.norms]}, sha256 {digest}")
 
 
+def make_table1_root():
+    t = time.time()
+    prob = Problem(91, 31, -9.0, 18.0, 9.0, F=0.7, eps=1.0)
+    pre = BlockPreconditioner(prob, prob.M - 1)
+    steps = continuation(prob, [0.1 * k for k in range(1, 11)], tol=1e-12, pre=pre, eta=1e-6)
+    for e, _, info in steps:
+        print(f"  eps {e:.1f}: converged {info.converged}, {info.newton} Newton, "
+              f"{info.gmres} GMRES, final {info.norms[-1]:.2e}", flush=True)
+    e, u, info = steps[-1]
+    if not info.converged or abs(e - 1.0) > 1e-12:
+        raise RuntimeError(f"oracle continuation stopped at eps {e}: {info}")
+    path, digest = _store("table1_91x31_eps1_root.npy", u)
+    print(f"wrote {path} in {time.time() - t:.1f} s, sha256 {digest}")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["linear", "root"]
+    which = sys.argv[1:] or ["linear", "root", "table1"]
     if "linear" in which:
         make_linear()
     if "root" in which:
         make_root()
+    if "table1" in which:
+        make_table1_root()

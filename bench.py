@@ -5,7 +5,8 @@ One step = one complete FP64 Jacobian-free Newton-Krylov solve of the largest
 workload, 721 x 241 on the paper's domain (x in [-14, 40], y in [0, 18],
 spacing 0.075, eps = 0.1, F = 0.7), from the flat surface to
 ||E||_inf <= 1e-10, including the set-up of the banded linear-Jacobian
-preconditioner (block half-bandwidth q, default 8) inside the step.  Inputs are
+preconditioner (block half-bandwidth q, default 16: a band of 1.2 in y, where
+GMRES per Newton step levels off) inside the step.  Inputs are
 synthetic (the flat state), device-resident before timing starts.
 
 Printed on one JSON line:
@@ -48,12 +49,17 @@ HBM_COUNTERS = "k_pairs_f64_721x241_hbm_counters.json"
 INST_COUNTERS = "k_pairs_f64_721x241_fp64_inst_counters.json"
 
 
+def inputs_q_large():
+    from paper_1403_5044_amd import inputs
+    return inputs.Q_BLOCKS[(inputs.CONFIG4["N"], inputs.CONFIG4["M"])]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--q", type=int, default=8,
+    ap.add_argument("--q", type=int, default=inputs_q_large(),
                     help="preconditioner block half-bandwidth of the benched solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -533,7 +539,7 @@ def residuals():
 def workloads():
     """Config 3: 361x121 on the paper's domain, F in {0.5, 0.7, 1.0} x eps in {0.1, 0.3},
     each solved in FP64 and in mixed precision with one preconditioner per F (q = 8).
-    Config 4: 721x241, F = 0.7, eps continued 0.1 -> 0.5 in mixed precision (q = 8), with
+    Config 4: 721x241, F = 0.7, eps continued 0.1 -> 0.5 in mixed precision (q = 16), with
     FP64 solves at the first and last eps for comparison."""
     import torch
     from paper_1403_5044_amd import api, inputs
@@ -572,7 +578,7 @@ def workloads():
                   file=sys.stderr, flush=True)
         P.close()
     c4 = inputs.CONFIG4
-    P, tb = build(c4, 8)
+    P, tb = build(c4, inputs.Q_BLOCKS[(c4["N"], c4["M"])])
     out["config4_build_s"] = tb
     u = None
     for eps in inputs.CONFIG4_EPS:
@@ -592,7 +598,7 @@ def workloads():
     n = len(out["config4"])
     total = sum(r["mixed"]["s"] for r in out["config4"])
     print(json.dumps(_line(n / total, "solves/s",
-                           "config-4 eps continuation 0.1..0.5 (721x241, mixed, q=8); "
+                           "config-4 eps continuation 0.1..0.5 (721x241, mixed, q=16); "
                            "config-3 F x eps grid in FP64 and mixed (361x121, q=8)",
                            {"runs": out}, dtype="f32+f64")), flush=True)
 
@@ -679,8 +685,8 @@ def table1():
     eps_list = [round(0.1 * k, 1) for k in range(1, 11)]
     runs = [("91x31", dict(N=91, M=31, **inputs.TABLE1[(91, 31)]), 0.7, "fp64", 30),
             ("361x121", dict(inputs.CONFIG3), 0.7, "fp64", 8),
-            ("721x241", dict(inputs.CONFIG4), 0.7, "fp32", 8),
-            ("721x241_F1.4", dict(inputs.CONFIG_F14), 1.4, "fp32", 8)]
+            ("721x241", dict(inputs.CONFIG4), 0.7, "fp32", 16),
+            ("721x241_F1.4", dict(inputs.CONFIG_F14), 1.4, "fp32", 16)]
     for name, cfg, F, prec, q in runs:
         cfg = dict(cfg)
         cfg.pop("eps", None)
@@ -728,7 +734,8 @@ def table1():
 def precond_study():
     """The preconditioner study (preconditioning section): GMRES iterations per
     Newton step against the block bandwidth b = 2q + 1 at 361 x 121 (eps = 1, F = 0.7,
-    from the eps = 0.9 root), and the spectra of J and J P^-1 on 45 x 13 (spacing 0.4,
+    from the eps = 0.9 root) and for cold solves of the benched 721 x 241 workload, and
+    the spectra of J and J P^-1 on 45 x 13 (spacing 0.4,
     x_1 = -9, eps = 1, F = 0.7, at the flat state) with J assembled from GPU JVP
     columns and P^-1 from preconditioner applies of the unit vectors."""
     import numpy as np
@@ -764,6 +771,23 @@ def precond_study():
         P.close()
         out["bandwidth_sweep"].append(r)
         log(f"b={2 * q + 1}: {r}")
+    # the same sweep on the finest mesh (spacing 0.075, half that of 361 x 121): cold FP64
+    # solves of the benched workload (eps = 0.1 from the flat surface), set-up included
+    c4 = dict(inputs.CONFIG4)
+    out["bandwidth_sweep_721x241"] = []
+    for q in (8, 12, 16, 20, 24):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = api.solve(c4["F"], c4["eps"], c4["N"], c4["M"], c4["x1"], c4["xN"],
+                               c4["yM"], q_blocks=q, **kw)
+        torch.cuda.synchronize()
+        r = {"b": 2 * q + 1, "q": q, "status": info.status, "newton": info.newton_iters,
+             "gmres": info.gmres_iters, "evals": info.residual_evals,
+             "gmres_per_newton": info.gmres_iters / max(1, info.newton_iters),
+             "build_s": info.time_precond_s, "solve_s": time.perf_counter() - t0,
+             "band_factor_bytes": c4["M"] * (2 * q + 1) * c4["N"] ** 2 * 8}
+        out["bandwidth_sweep_721x241"].append(r)
+        log(f"721x241 b={2 * q + 1}: {r}")
     # spectra on 45 x 13
     N, M = 45, 13
     c = dict(N=N, M=M, x1=-9.0, xN=-9.0 + 0.4 * (N - 1), yM=0.4 * (M - 1), F=0.7, eps=1.0)

@@ -595,6 +595,10 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 // reciprocal) in a double-buffered LDS slot; after the barrier every thread takes the
 // best of the 4 posts.  It writes the new panel columns pn[N][kPWG], the old pivot rows
 // z[kPWG][N], step_of[N] and rowpiv[N] (per block, in the workspace).
+// The step loop is not unrolled (an unrolled one is ~9K instructions, far beyond the
+// instruction cache, and ran at ~90 us per panel): instead each step works on register
+// column 0 and writes its results shifted down by one column, so that the panel
+// columns rotate through the registers and are back in place after kPWG steps.
 constexpr int kGP = 256;
 constexpr int kPWG = 16;
 
@@ -614,7 +618,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     double* z = w.z + (size_t)blockIdx.x * kPWG * N;
     int* step_of = w.piv + (size_t)blockIdx.x * 2 * N;
     int* rowpiv = step_of + N;
-    __shared__ double rec[2][NW][kPWG + 1];  // scaled candidate row, then its pivot value
+    __shared__ double rec[2][NW][kPWG + 1];  // scaled candidate row (rotated), then its pivot
     __shared__ int ckey[2][NW], crow[2][NW], rp_s[kPWG];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int kb = min(kPWG, N - k0);
@@ -630,14 +634,15 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
             pv[i][u] = (valid && u < kb) ? B[(size_t)r * N + k0 + u] : 0.0;
     }
     int zeros = 0;
-#pragma unroll
-    for (int s = 0; s < kPWG; ++s) {
-        if (s >= kb) continue;  // uniform; keeps the trip count constant for full unrolling
+    // step s: register column 0 holds panel column s; register column u holds panel
+    // column (s + u) mod kPWG
+#pragma unroll 1
+    for (int s = 0; s < kb; ++s) {
         const int buf = s & 1;
         int key = -1, bi = -1;
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int kk = pivot_key(pv[i][s]);
+            const int kk = pivot_key(pv[i][0]);
             if (st[i] < 0 && kk > key) {
                 key = kk;
                 bi = i;
@@ -647,14 +652,19 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         const unsigned long long mask = __ballot(bi >= 0 && key == wm);
         const int wl = mask ? __builtin_ctzll(mask) : -1;
         if (lane == wl) {
+            double row[kPWG];
 #pragma unroll
-            for (int i = 0; i < RW; ++i)
-                if (i == bi) {
-                    const double d = rcp64(pv[i][s]);
+            for (int u = 0; u < kPWG; ++u) row[u] = pv[0][u];
 #pragma unroll
-                    for (int u = 0; u < kPWG; ++u) rec[buf][wv][u] = (u == s) ? d : pv[i][u] * d;
-                    rec[buf][wv][kPWG] = pv[i][s];
-                }
+            for (int i = 1; i < RW; ++i)
+                if (i == bi)
+#pragma unroll
+                    for (int u = 0; u < kPWG; ++u) row[u] = pv[i][u];
+            const double d = rcp64(row[0]);
+            rec[buf][wv][0] = d;
+#pragma unroll
+            for (int u = 1; u < kPWG; ++u) rec[buf][wv][u] = row[u] * d;
+            rec[buf][wv][kPWG] = row[0];
         }
         if (lane == 0) {
             ckey[buf][wv] = mask ? wm : -1;
@@ -674,23 +684,37 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         double pd[kPWG];
 #pragma unroll
         for (int u = 0; u < kPWG; ++u) pd[u] = rec[buf][gw][u];
-        const double d = pd[s];
+        const double d = pd[0];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             if (t + kGP * i == rp) {
+                // the pivot row becomes the scaled row; column s takes 1/pivot
 #pragma unroll
-                for (int u = 0; u < kPWG; ++u) pv[i][u] = pd[u];
+                for (int u = 0; u + 1 < kPWG; ++u) pv[i][u] = pd[u + 1];
+                pv[i][kPWG - 1] = d;
                 st[i] = k0 + s;
             } else {
-                const double m = pv[i][s];
+                const double m = pv[i][0];
 #pragma unroll
-                for (int u = 0; u < kPWG; ++u) pv[i][u] = (u == s) ? -m * d : fma(-m, pd[u], pv[i][u]);
+                for (int u = 0; u + 1 < kPWG; ++u) pv[i][u] = fma(-m, pd[u + 1], pv[i][u + 1]);
+                pv[i][kPWG - 1] = -m * d;
             }
         }
         if (t == 0) {
             rp_s[s] = rp;
             rowpiv[k0 + s] = rp;
             if (!(fabs(rec[buf][gw][kPWG]) > 0.0)) ++zeros;
+        }
+    }
+    // a short last panel: kb rotations done, kPWG - kb more put the columns back in place
+#pragma unroll 1
+    for (int s = kb; s < kPWG; ++s) {
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const double c0 = pv[i][0];
+#pragma unroll
+            for (int u = 0; u + 1 < kPWG; ++u) pv[i][u] = pv[i][u + 1];
+            pv[i][kPWG - 1] = c0;
         }
     }
 #pragma unroll
@@ -703,9 +727,9 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         }
     }
     __syncthreads();
-    for (int e = t; e < kb * N; e += kGP) {
-        const int tt = e / N, j = e - tt * N;
-        z[(size_t)tt * N + j] = B[(size_t)rp_s[tt] * N + j];
+    for (int tt = 0; tt < kb; ++tt) {
+        const double* src = B + (size_t)rp_s[tt] * N;
+        for (int j = t; j < N; j += kGP) z[(size_t)tt * N + j] = src[j];
     }
     if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
@@ -919,6 +943,8 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
             for (int k0 = 0; k0 < N; k0 += kPWG) {
                 if (N <= 2 * kGP)
                     k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                else if (N <= 3 * kGP)
+                    k_gjp_panel<3><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
                 else
                     k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
                 k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);

@@ -32,6 +32,9 @@ CONFIG4 = dict(N=721, M=241, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
 CONFIG4_EPS = (0.1, 0.2, 0.3, 0.4, 0.5)
 # F = 1.4 on 721 x 241 with spacing 0.3 from x_1 = -56 (the paper's F = 1.4 surface)
 CONFIG_F14 = dict(N=721, M=241, x1=-56.0, xN=160.0, yM=72.0, F=1.4, eps=1.0)
+# Block half-bandwidth of the preconditioner on the paper's domain: the band that
+# matters is a distance in y (1.2 here), so it doubles when the spacing halves
+Q_BLOCKS = {(361, 121): 8, (721, 241): 16}
 # Solver settings of the large-mesh solves (361 x 121 and beyond)
 LARGE_SOLVE = dict(tol=1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
 SERVING_MESHES = ((61, 21), (121, 41), (181, 61), (241, 81))

@@ -47,7 +47,7 @@ def test_config3_root_satisfies_the_oracle_and_mixed_agrees():
 
 def test_config4_continuation_step_satisfies_the_oracle():
     cfg = inputs.CONFIG4
-    P = api.Preconditioner(api.Problem(**cfg), 8)
+    P = api.Preconditioner(api.Problem(**cfg), inputs.Q_BLOCKS[(cfg["N"], cfg["M"])])
     um, zm, im = _solve(cfg, cfg["F"], 0.1, "fp32", P)
     assert im.status == 0
     u2, z2, i2 = _solve(cfg, cfg["F"], 0.2, "fp32", P, u0=um)

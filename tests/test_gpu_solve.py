@@ -158,8 +158,8 @@ def test_preconditioner_graph_replays_match_the_dense_solve():
 
 
 @pytest.mark.parametrize("N,M", [(64, 6), (65, 7), (121, 9), (181, 7), (182, 5), (183, 5),
-                                 (192, 5), (241, 5), (256, 4), (257, 4), (521, 4), (667, 4),
-                                 (721, 4), (1024, 4)])
+                                 (192, 5), (241, 5), (256, 4), (257, 4), (512, 4), (521, 4),
+                                 (667, 4), (721, 4), (768, 4), (769, 4), (1024, 4)])
 def test_preconditioner_wide_blocks_match_dense_solve(N, M):
     """Every diagonal-block inversion variant against the oracle's dense P: the
     register-tile kernel with 1, 2 and 3 panel rows per lane (13- and 14-row tiles on

@@ -405,6 +405,7 @@ __device__ __forceinline__ void gj_stage(int lane, int k0, int kb, const double 
 template <int RB, int CB, int RW>
 __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ base, size_t stride,
                                                  int* __restrict__ info) {
+    __builtin_amdgcn_s_setprio(3);  // the inversion chain is the set-up's critical path
     constexpr int R = 14 * RB, C = 32 * CB;
     constexpr int RP = (R > 64 * RW) ? R : 64 * RW;  // rows of the panel buffers
     double* A = base + (size_t)blockIdx.x * stride;
@@ -612,6 +613,7 @@ template <int RW>
 __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restrict__ base,
                                                    size_t stride, GjWork w, int k0,
                                                    int* __restrict__ info) {
+    __builtin_amdgcn_s_setprio(3);  // the inversion chain is the set-up's critical path
     constexpr int NW = kGP / 64;
     const double* B = base + (size_t)blockIdx.x * stride;
     double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
@@ -727,10 +729,24 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         }
     }
     __syncthreads();
-    for (int tt = 0; tt < kb; ++tt) {
-        const double* src = B + (size_t)rp_s[tt] * N;
-        for (int j = t; j < N; j += kGP) z[(size_t)tt * N + j] = src[j];
+    // the old pivot rows: every load issued before the first store (a load-store loop
+    // would wait out one memory latency per element)
+#pragma unroll
+    for (int tt = 0; tt < kPWG; ++tt) {
+        const double* src = B + (size_t)rp_s[min(tt, kb - 1)] * N;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int j = t + kGP * i;
+            pv[i][tt] = (tt < kb && j < N) ? src[j] : 0.0;
+        }
     }
+#pragma unroll
+    for (int tt = 0; tt < kPWG; ++tt)
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int j = t + kGP * i;
+            if (tt < kb && j < N) z[(size_t)tt * N + j] = pv[i][tt];
+        }
     if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
 }
 
@@ -747,6 +763,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
 __global__ __launch_bounds__(kGP) void k_gjs_step(int N, double* __restrict__ base, size_t stride,
                                                   GjWork w, int kp, int kn,
                                                   int* __restrict__ info) {
+    __builtin_amdgcn_s_setprio(3);  // the inversion chain is the set-up's critical path
     constexpr int RW = kGP / 64;  // panel rows per lane: 64 RW >= N
     double* B = base + (size_t)blockIdx.y * stride;
     int* step_of = w.piv + (size_t)blockIdx.y * 2 * N;
@@ -840,6 +857,7 @@ __global__ __launch_bounds__(kGP) void k_gjs_step(int N, double* __restrict__ ba
 // Tile of 16 rows x 64 columns per 256-thread workgroup; grid (cols, rows, blocks).
 __global__ __launch_bounds__(256) void k_gjp_update(int N, double* __restrict__ base,
                                                     size_t stride, GjWork w, int k0) {
+    __builtin_amdgcn_s_setprio(3);  // the inversion chain is the set-up's critical path
     double* B = base + (size_t)blockIdx.z * stride;
     const double* pn = w.pn + (size_t)blockIdx.z * N * kPWG;
     const double* z = w.z + (size_t)blockIdx.z * kPWG * N;

@@ -333,17 +333,18 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
             for (int t = i0 * 4 + tid; t < i1 * 4; t += kPairThreads) dst[t] = srow[t];
         }
         __syncthreads();
-        double dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
+        double dy[CP], dyp[CP], dy2[CP], ddy[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
 #pragma unroll
         for (int c = 0; c < CP; ++c) {
             dy[c] = (double)(j - lrow[c]) * g.dy;
             dyp[c] = (double)(j + lrow[c]) * g.dy;
             dy2[c] = dy[c] * dy[c];
-            dyp2[c] = dyp[c] * dyp[c];
+            // (y + y*)^2 - (y - y*)^2 = 4 j l dy^2: the image distance from the direct one
+            ddy[c] = (double)(4 * j * lrow[c]) * (g.dy * g.dy);
             Bdy[c] = B[c] * dy[c];
             mBdyp[c] = -B[c] * dyp[c];
             Cdy2[c] = C[c] * dy2[c];
-            Cdyp2[c] = C[c] * dyp2[c];
+            Cdyp2[c] = C[c] * (dyp[c] * dyp[c]);
         }
 #pragma unroll SW_UNROLL64
         for (int i = i0; i < i1; ++i) {
@@ -354,13 +355,12 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
                 const double dx = sx - xs[c];
-                const double dx2 = dx * dx;
                 const double dz = sz - zs[c];
-                const double h = fma(dz, dz, dx2);
+                const double rr = fma(dx, dx, fma(dz, dz, dy2[c]));
                 // doubled reciprocal distances: i = 2/r, and the sum j1s + j2s of the
                 // doubled 2/sqrt(q), whose last Newton products share one fma
-                const double i1 = rsq2_64(h + dy2[c]);
-                const double i2 = rsq2_64(h + dyp2[c]);
+                const double i1 = rsq2_64(rr);
+                const double i2 = rsq2_64(rr + ddy[c]);
                 const double q1 = fma(dx, fma(A[c], dx, Bdy[c]), Cdy2[c]);
                 const double q2 = fma(dx, fma(A[c], dx, mBdyp[c]), Cdyp2[c]);
                 const double y1 = __builtin_amdgcn_rsq(q1);
@@ -446,18 +446,18 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
             for (int t = i0 * 2 + tid; t < i1 * 2; t += kPairThreads) dst[t] = srow[t];
         }
         __syncthreads();
-        float dy[CP], dyp[CP], dy2[CP], dyp2[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
+        float dy[CP], dyp[CP], dy2[CP], ddy[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
         float r1[CP], r2[CP], r3[CP];
 #pragma unroll
         for (int c = 0; c < CP; ++c) {
             dy[c] = (float)(j - lrow[c]) * (float)g.dy;
             dyp[c] = (float)(j + lrow[c]) * (float)g.dy;
             dy2[c] = dy[c] * dy[c];
-            dyp2[c] = dyp[c] * dyp[c];
+            ddy[c] = (float)(4 * j * lrow[c]) * ((float)g.dy * (float)g.dy);
             Bdy[c] = B[c] * dy[c];
             mBdyp[c] = -B[c] * dyp[c];
             Cdy2[c] = C[c] * dy2[c];
-            Cdyp2[c] = C[c] * dyp2[c];
+            Cdyp2[c] = C[c] * (dyp[c] * dyp[c]);
             r1[c] = r2[c] = r3[c] = 0.0f;
         }
 #pragma unroll 2
@@ -467,11 +467,10 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
                 const float dx = (s0.x + t0[c]) * fdx;
-                const float dx2 = dx * dx;
                 const float dz = s0.y - zs[c];
-                const float h = fmaf(dz, dz, dx2);
-                const float i1 = __builtin_amdgcn_rsqf(h + dy2[c]);
-                const float i2 = __builtin_amdgcn_rsqf(h + dyp2[c]);
+                const float rr = fmaf(dx, dx, fmaf(dz, dz, dy2[c]));
+                const float i1 = __builtin_amdgcn_rsqf(rr);
+                const float i2 = __builtin_amdgcn_rsqf(rr + ddy[c]);
                 const float q1 = fmaf(dx, fmaf(A[c], dx, Bdy[c]), Cdy2[c]);
                 const float q2 = fmaf(dx, fmaf(A[c], dx, mBdyp[c]), Cdyp2[c]);
                 const float j1s = __builtin_amdgcn_rsqf(q1);

@@ -989,12 +989,10 @@ struct GemmBatch {
 
 // FP64 matrix cores (v_mfma_f64_16x16x4f64): four wavefronts per workgroup in a 2 x 2
 // arrangement, each computing WM x WN MFMA tiles of 16 x 16 (a (32 WM) x (32 WN) tile of C
-// per workgroup; 64 x 64 for blocks with N > 256).  K is staged through two LDS buffers
-// kGK at a time: the next slice is loaded into registers while the MFMAs read the current
-// buffer, then written to the other buffer, so there is one barrier per slice.  Both
-// operands are stored k-major in LDS (a 16-row MFMA fragment is then 16 consecutive
-// doubles).  Operand layout of the instruction: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; result register r of lane l is C[l / 16 + 4 r][l % 16].
+// per workgroup; 64 x 64 for blocks with N > 256), K staged through LDS kGK at a time with
+// the next slice prefetched into registers.  Operand layout of the instruction: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// C[l / 16 + 4 r][l % 16].
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int WM, int WN, int kGK>
@@ -1013,8 +1011,8 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
         }
         return;
     }
-    __shared__ double As[2][kGK][TM];
-    __shared__ double Bs[2][kGK][TN];
+    __shared__ double As[TM][kGK + 1];
+    __shared__ double Bs[kGK][TN + 2];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
     const int wr = (w >> 1) * 16 * WM, wc = (w & 1) * 16 * WN;
@@ -1023,8 +1021,8 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
     for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    const int ar = t / (kGK / EA), ak = (t % (kGK / EA)) * EA;  // A slice TM x kGK
-    const int bk = t / (TN / EB), bc = (t % (TN / EB)) * EB;    // B slice kGK x TN
+    const int ar = t / (kGK / EA), ak = (t % (kGK / EA)) * EA;  // A slice TM x 16
+    const int bk = t / (TN / EB), bc = (t % (TN / EB)) * EB;    // B slice 16 x TN
     double ra[EA], rb[EB];
     auto load = [&](int k0) {
 #pragma unroll
@@ -1038,36 +1036,28 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
             rb[e] = (gk < n && gc < n) ? B[(size_t)gk * n + gc] : 0.0;
         }
     };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < EA; ++e) As[buf][ak + e][ar] = ra[e];
-#pragma unroll
-        for (int e = 0; e < EB; ++e) Bs[buf][bk][bc + e] = rb[e];
-    };
     load(0);
-    store(0);
-    __syncthreads();
-    int buf = 0;
     for (int k0 = 0; k0 < n; k0 += kGK) {
-        const bool more = k0 + kGK < n;
-        if (more) load(k0 + kGK);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EA; ++e) As[ar][ak + e] = ra[e];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) Bs[bk][bc + e] = rb[e];
+        __syncthreads();
+        if (k0 + kGK < n) load(k0 + kGK);
 #pragma unroll
         for (int k4 = 0; k4 < kGK; k4 += 4) {
             double fa[WM], fb[WN];
 #pragma unroll
-            for (int a = 0; a < WM; ++a) fa[a] = As[buf][k4 + (lane >> 4)][wr + a * 16 + (lane & 15)];
+            for (int a = 0; a < WM; ++a) fa[a] = As[wr + a * 16 + (lane & 15)][k4 + (lane >> 4)];
 #pragma unroll
-            for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+            for (int b = 0; b < WN; ++b) fb[b] = Bs[k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < WM; ++a)
 #pragma unroll
                 for (int b = 0; b < WN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
-        // the buffer written here was last read before the previous iteration's barrier
-        if (more) store(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
     }
     const double* Cin = job.Cin;
     double* C = job.C;

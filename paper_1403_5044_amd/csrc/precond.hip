@@ -590,8 +590,8 @@ __global__ __launch_bounds__(kGT) void k_gj_tile(int N, double* __restrict__ bas
 }
 
 // ---- N > 192: the block in global memory, one panel and one update launch per panel ----
-// Panel kernel: one 256-thread workgroup per block; thread t holds panel rows
-// t + 256 i (i < RW, N <= 256 RW).  One block barrier per step: every wavefront posts
+// Panel kernel: one NT-thread workgroup per block; thread t holds panel rows
+// t + NT i (i < RW, N <= NT RW).  One block barrier per step: every wavefront posts
 // its best candidate (key, row, and the row already scaled by the candidate's
 // reciprocal) in a double-buffered LDS slot; after the barrier every thread takes the
 // best of the 4 posts.  It writes the new panel columns pn[N][kPWG], the old pivot rows
@@ -609,12 +609,12 @@ struct GjWork {
     int* piv;     // [nblocks][2][N]: step_of, rowpiv
 };
 
-template <int RW>
-__global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restrict__ base,
+template <int RW, int NT>
+__global__ __launch_bounds__(NT) void k_gjp_panel(int N, const double* __restrict__ base,
                                                    size_t stride, GjWork w, int k0,
                                                    int* __restrict__ info) {
     __builtin_amdgcn_s_setprio(3);  // the inversion chain is the set-up's critical path
-    constexpr int NW = kGP / 64;
+    constexpr int NW = NT / 64;
     const double* B = base + (size_t)blockIdx.x * stride;
     double* pn = w.pn + (size_t)blockIdx.x * N * kPWG;
     double* z = w.z + (size_t)blockIdx.x * kPWG * N;
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     double pv[RW][kPWG];
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
-        const int r = t + kGP * i;
+        const int r = t + NT * i;
         const bool valid = r < N;
         st[i] = valid ? ((k0 > 0) ? step_of[r] : -1) : N;  // N marks padding
 #pragma unroll
@@ -668,9 +668,12 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
             for (int u = 1; u < kPWG; ++u) rec[buf][wv][u] = row[u] * d;
             rec[buf][wv][kPWG] = row[0];
         }
+        // read the candidate's row slot with every lane active: inside the lane-0 branch
+        // below the other lanes of bi need not hold a value
+        const int bsel = __builtin_amdgcn_readlane(bi, max(wl, 0));
         if (lane == 0) {
             ckey[buf][wv] = mask ? wm : -1;
-            crow[buf][wv] = mask ? wv * 64 + wl + kGP * max(0, __builtin_amdgcn_readlane(bi, max(wl, 0))) : -1;
+            crow[buf][wv] = mask ? wv * 64 + wl + NT * max(0, bsel) : -1;
         }
         __syncthreads();
         int gw = 0, gk = ckey[buf][0];
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         const double d = pd[0];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            if (t + kGP * i == rp) {
+            if (t + NT * i == rp) {
                 // the pivot row becomes the scaled row; column s takes 1/pivot
 #pragma unroll
                 for (int u = 0; u + 1 < kPWG; ++u) pv[i][u] = pd[u + 1];
@@ -721,7 +724,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     }
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
-        const int r = t + kGP * i;
+        const int r = t + NT * i;
         if (r < N) {
 #pragma unroll
             for (int u = 0; u < kPWG; ++u) pn[(size_t)r * kPWG + u] = pv[i][u];
@@ -736,7 +739,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
         const double* src = B + (size_t)rp_s[min(tt, kb - 1)] * N;
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int j = t + kGP * i;
+            const int j = t + NT * i;
             pv[i][tt] = (tt < kb && j < N) ? src[j] : 0.0;
         }
     }
@@ -744,7 +747,7 @@ __global__ __launch_bounds__(kGP) void k_gjp_panel(int N, const double* __restri
     for (int tt = 0; tt < kPWG; ++tt)
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
-            const int j = t + kGP * i;
+            const int j = t + NT * i;
             if (tt < kb && j < N) z[(size_t)tt * N + j] = pv[i][tt];
         }
     if (t == 0 && info) info[blockIdx.x] = (k0 == 0 ? 0 : info[blockIdx.x]) + zeros;
@@ -959,12 +962,14 @@ void gj_inverse(int N, double* base, size_t stride, int nblocks, int* info, doub
         } else {
             const dim3 ug((N + 63) / 64, (N + 15) / 16, nblocks);
             for (int k0 = 0; k0 < N; k0 += kPWG) {
+                // four wavefronts with two to four panel rows per thread (one row per thread
+                // in 8-16 wavefronts measured 2.5x slower per panel at N = 721)
                 if (N <= 2 * kGP)
-                    k_gjp_panel<2><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                    k_gjp_panel<2, kGP><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
                 else if (N <= 3 * kGP)
-                    k_gjp_panel<3><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                    k_gjp_panel<3, kGP><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
                 else
-                    k_gjp_panel<4><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
+                    k_gjp_panel<4, kGP><<<nblocks, kGP, 0, s>>>(N, base, stride, w, k0, info);
                 k_gjp_update<<<ug, 256, 0, s>>>(N, base, stride, w, k0);
             }
         }

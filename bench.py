@@ -775,7 +775,7 @@ def precond_study():
     # solves of the benched workload (eps = 0.1 from the flat surface), set-up included
     c4 = dict(inputs.CONFIG4)
     out["bandwidth_sweep_721x241"] = []
-    for q in (8, 12, 16, 20, 24):
+    for q in (8, 12, 14, 16, 18, 20, 24):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, info = api.solve(c4["F"], c4["eps"], c4["N"], c4["M"], c4["x1"], c4["xN"],

@@ -1317,6 +1317,74 @@ __global__ __launch_bounds__(64 * kWaves) void k_band_pair(int N, const BandStep
     }
 }
 
+// The same step with the whole workgroup on each term: a workgroup computes kR
+// consecutive output rows of one block row; thread t takes columns t + 256 c of each
+// term (c < kCols, 256 kCols >= N), so that a term is one round of loads for all kR rows
+// instead of N / 64 dependent ones per row, the term's vector is read once for the kR
+// rows, and kTU terms are in flight together.  The per-thread sums are added across the
+// workgroup in a fixed order.
+template <int kCols, int kTU, int kR>
+__global__ __launch_bounds__(256) void k_band_row(int N, const BandStep st) {
+    const int nrb = (N + kR - 1) / kR;  // row groups per block row
+    const int i = blockIdx.x / nrb;
+    const int r0 = (blockIdx.x - i * nrb) * kR;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t0 = st.first[i], t1 = st.first[i + 1];
+    double s[kR];
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) s[rr] = 0.0;
+    for (int u = t0; u < t1; u += kTU) {
+        double p[kTU][kR];
+#pragma unroll
+        for (int k = 0; k < kTU; ++k) {
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) p[k][rr] = 0.0;
+            if (u + k < t1) {
+                const double* b = st.blk[u + k];
+                const double* v = st.vec[u + k];
+#pragma unroll
+                for (int c = 0; c < kCols; ++c) {
+                    const int n = t + 256 * c;
+                    if (n < N) {
+                        const double vn = v[n];
+#pragma unroll
+                        for (int rr = 0; rr < kR; ++rr)
+                            if (r0 + rr < N)
+                                p[k][rr] = fma(b[(size_t)(r0 + rr) * N + n], vn, p[k][rr]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTU; ++k)
+            if (u + k < t1)
+#pragma unroll
+                for (int rr = 0; rr < kR; ++rr) s[rr] = fma(st.sign[u + k], p[k][rr], s[rr]);
+    }
+    __shared__ double part[kR][4];
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) {
+        double x = s[rr];
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+        if (lane == 0) part[rr][w] = x;
+    }
+    __syncthreads();
+    if (t < kR && r0 + t < N) {
+        const double sum = (part[t][0] + part[t][1]) + (part[t][2] + part[t][3]);
+        st.out[i][r0 + t] = (st.add[i] ? st.add[i][r0 + t] : 0.0) + sum;
+    }
+}
+
+// At 721 x 241, q = 16, one apply takes 8.2 ms with k_band_row (2 terms in flight, one
+// output row per workgroup) against 10.4 ms with k_band_pair; two or four rows per
+// workgroup (fewer workgroups) took 13.1 and 23.1 ms.
+#ifndef SW_BAND_ROW_TU
+#define SW_BAND_ROW_TU 2  // terms in flight per thread in k_band_row (0: k_band_pair)
+#endif
+#ifndef SW_BAND_ROW_R
+#define SW_BAND_ROW_R 1   // output rows per workgroup in k_band_row
+#endif
+
 // q = 0: x_l = Dinv_l t_l for all l at once (wavefront per output row).
 __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const double* __restrict__ S,
                                                         const double* __restrict__ t,
@@ -2105,9 +2173,19 @@ void enqueue_substitution(const sw_precond* P, hipStream_t s) {
         return;
     }
     if (!P->band_steps.empty()) {
-        for (const BandStep& st : P->band_steps)
-            k_band_pair<SW_BAND_WAVES>
-                <<<(unsigned)(st.nrow * N), 64 * SW_BAND_WAVES, 0, s>>>(N, st);
+        for (const BandStep& st : P->band_steps) {
+#if SW_BAND_ROW_TU > 0
+            constexpr int kR = SW_BAND_ROW_R;
+            const unsigned grid = (unsigned)(st.nrow * ((N + kR - 1) / kR));
+            if (N <= 768)
+                k_band_row<3, SW_BAND_ROW_TU, kR><<<grid, 256, 0, s>>>(N, st);
+            else if (N <= 1024)
+                k_band_row<4, SW_BAND_ROW_TU, kR><<<grid, 256, 0, s>>>(N, st);
+            else
+#endif
+                k_band_pair<SW_BAND_WAVES>
+                    <<<(unsigned)(st.nrow * N), 64 * SW_BAND_WAVES, 0, s>>>(N, st);
+        }
         return;
     }
     const GemvTerm* terms = static_cast<const GemvTerm*>(P->terms);

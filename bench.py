@@ -51,7 +51,7 @@ INST_COUNTERS = "k_pairs_f64_721x241_fp64_inst_counters.json"
 
 def inputs_q_large():
     from paper_1403_5044_amd import inputs
-    return inputs.Q_BLOCKS[(inputs.CONFIG4["N"], inputs.CONFIG4["M"])]
+    return inputs.Q_BLOCKS[(inputs.W721X241["N"], inputs.W721X241["M"])]
 
 
 def parse():
@@ -69,9 +69,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--residuals", action="store_true",
-                    help="residual throughput on configs 1-4, FP64 and FP32-Kahan (own line)")
+                    help="residual throughput on the 31x11, 181x61, 361x121 and 721x241 workloads, "
+                         "FP64 and FP32-Kahan (own line)")
     ap.add_argument("--workloads", action="store_true",
-                    help="config-3 solves (F x eps grid, FP64 and mixed) and the config-4 "
+                    help="361x121 solves (F x eps grid, FP64 and mixed) and the 721x241 "
                          "eps continuation (own line)")
     ap.add_argument("--table1", action="store_true",
                     help="the paper's eps = 1, F = 0.7 workload: per-evaluation times on the "
@@ -192,7 +193,7 @@ def cpu_baseline(cfg, evals_per_solve):
     from oracle import flat_state as oflat
     from oracle.solve import newton
     from paper_1403_5044_amd import inputs
-    c1 = inputs.CONFIG1
+    c1 = inputs.W31X11
     op1 = OProblem(c1["N"], c1["M"], c1["x1"], c1["xN"], c1["yM"], F=c1["F"], eps=c1["eps"])
     t0 = time.perf_counter()
     _, oinfo = newton(op1, oflat(op1), tol=1e-10)
@@ -260,7 +261,7 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    cfg = inputs.CONFIG4
+    cfg = inputs.W721X241
     N, M = cfg["N"], cfg["M"]
     solve_kw = dict(q_blocks=args.q, **inputs.LARGE_SOLVE)
 
@@ -378,8 +379,8 @@ def extra_measurements(api, inputs, cfg, one_solve, z64, args):
 
     p4 = api.Problem(**cfg)
     u4 = [torch.tensor(inputs.smooth_state(p4.N, p4.M, 0.02, 1), device="cuda")]
-    c2 = api.Problem(**inputs.CONFIG2)
-    batch = [torch.tensor(u, device="cuda") for u in inputs.config2_batch(16)]
+    c2 = api.Problem(**inputs.W181X61)
+    batch = [torch.tensor(u, device="cuda") for u in inputs.batch_181x61(16)]
     for prec in ("fp64", "fp32"):
         ms = timed_residuals(p4.with_(precision=prec), u4, 3)
         res[f"residual_{p4.N}x{p4.M}_{prec}_ms"] = ms
@@ -504,15 +505,16 @@ def _line(value, unit, workload, extra, dtype="f64", higher=True):
 
 
 def residuals():
-    """Whole-residual throughput (prelude, pair sum and finish) on configs 1-4 from a
+    """Whole-residual throughput (prelude, pair sum and finish) on the 31x11, 181x61, 361x121
+    and 721x241 workloads from a
     smooth synthetic state, each precision timed over repeated calls with HIP events."""
     import torch
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
     _lib.load()
     rows = {}
-    for name, cfg, reps in (("config1", inputs.CONFIG1, 50), ("config2", inputs.CONFIG2, 50),
-                            ("config3", inputs.CONFIG3, 10), ("config4", inputs.CONFIG4, 3)):
+    for name, cfg, reps in (("31x11", inputs.W31X11, 50), ("181x61", inputs.W181X61, 50),
+                            ("361x121", inputs.W361X121, 10), ("721x241", inputs.W721X241, 3)):
         for prec in ("fp64", "fp32"):
             p = api.Problem(**cfg, precision=prec)
             u = torch.tensor(inputs.smooth_state(p.N, p.M, 0.02, 1), device="cuda")
@@ -531,15 +533,16 @@ def residuals():
                 "algorithmic_tflops": FLOP_PER_PAIR * p.pairs / ms * 1e-9,
                 "frac_of_peak": FLOP_PER_PAIR * p.pairs / ms * 1e-9 /
                 (FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else 2 * FP64_VECTOR_PEAK_TFLOPS)}
-    print(json.dumps(_line(rows["config4_fp64"]["pairs_per_s"], "pairs/s",
-                           "whole residual E(u) on configs 1-4 (smooth state), FP64 and FP32-Kahan",
+    print(json.dumps(_line(rows["721x241_fp64"]["pairs_per_s"], "pairs/s",
+                           "whole residual E(u) on 31x11, 181x61, 361x121 and 721x241 (smooth "
+                           "state), FP64 and FP32-Kahan",
                            {"rows": rows})), flush=True)
 
 
 def workloads():
-    """Config 3: 361x121 on the paper's domain, F in {0.5, 0.7, 1.0} x eps in {0.1, 0.3},
+    """361x121 on the paper's domain, F in {0.5, 0.7, 1.0} x eps in {0.1, 0.3},
     each solved in FP64 and in mixed precision with one preconditioner per F (q = 8).
-    Config 4: 721x241, F = 0.7, eps continued 0.1 -> 0.5 in mixed precision (q = 16), with
+    721x241, F = 0.7, eps continued 0.1 -> 0.5 in mixed precision (q = 16), with
     FP64 solves at the first and last eps for comparison."""
     import torch
     from paper_1403_5044_amd import api, inputs
@@ -565,41 +568,41 @@ def workloads():
         torch.cuda.synchronize()
         return P, time.perf_counter() - t0
 
-    out = {"config3": [], "config4": []}
-    c3 = inputs.CONFIG3
-    for F in inputs.CONFIG3_F:
+    out = {"361x121": [], "721x241": []}
+    c3 = inputs.W361X121
+    for F in inputs.W361X121_F:
         P, tb = build(dict(c3, F=F), 8)
-        for eps in inputs.CONFIG3_EPS:
+        for eps in inputs.W361X121_EPS:
             _, z64, r64 = timed(F, eps, c3, "fp64", P)
             _, z32, r32 = timed(F, eps, c3, "fp32", P)
-            out["config3"].append({"F": F, "eps": eps, "build_s": tb, "fp64": r64, "mixed": r32,
+            out["361x121"].append({"F": F, "eps": eps, "build_s": tb, "fp64": r64, "mixed": r32,
                                    "zeta_mixed_vs_fp64": (z64 - z32).abs().max().item()})
-            print(f"config3 F={F} eps={eps}: fp64 {r64['s']:.2f}s mixed {r32['s']:.2f}s",
+            print(f"361x121 F={F} eps={eps}: fp64 {r64['s']:.2f}s mixed {r32['s']:.2f}s",
                   file=sys.stderr, flush=True)
         P.close()
-    c4 = inputs.CONFIG4
+    c4 = inputs.W721X241
     P, tb = build(c4, inputs.Q_BLOCKS[(c4["N"], c4["M"])])
-    out["config4_build_s"] = tb
+    out["721x241_build_s"] = tb
     u = None
-    for eps in inputs.CONFIG4_EPS:
+    for eps in inputs.W721X241_EPS:
         um, zm, rm = timed(c4["F"], eps, c4, "fp32", P, u)
         rec = {"eps": eps, "mixed": rm}
-        if eps in (inputs.CONFIG4_EPS[0], inputs.CONFIG4_EPS[-1]):
+        if eps in (inputs.W721X241_EPS[0], inputs.W721X241_EPS[-1]):
             _, z64, r64 = timed(c4["F"], eps, c4, "fp64", P, u)
             rec["fp64"] = r64
             rec["zeta_mixed_vs_fp64"] = (z64 - zm).abs().max().item()
-        out["config4"].append(rec)
-        print(f"config4 eps={eps}: mixed {rm['s']:.2f}s status {rm['status']}", file=sys.stderr,
+        out["721x241"].append(rec)
+        print(f"721x241 eps={eps}: mixed {rm['s']:.2f}s status {rm['status']}", file=sys.stderr,
               flush=True)
         if rm["status"] != 0:
             break
         u = um
     P.close()
-    n = len(out["config4"])
-    total = sum(r["mixed"]["s"] for r in out["config4"])
+    n = len(out["721x241"])
+    total = sum(r["mixed"]["s"] for r in out["721x241"])
     print(json.dumps(_line(n / total, "solves/s",
-                           "config-4 eps continuation 0.1..0.5 (721x241, mixed, q=16); "
-                           "config-3 F x eps grid in FP64 and mixed (361x121, q=8)",
+                           "721x241 eps continuation 0.1..0.5 (mixed, q=16); "
+                           "361x121 F x eps grid in FP64 and mixed (q=8)",
                            {"runs": out}, dtype="f32+f64")), flush=True)
 
 
@@ -684,9 +687,9 @@ def table1():
     kw = dict(inputs.LARGE_SOLVE)
     eps_list = [round(0.1 * k, 1) for k in range(1, 11)]
     runs = [("91x31", dict(N=91, M=31, **inputs.TABLE1[(91, 31)]), 0.7, "fp64", 30),
-            ("361x121", dict(inputs.CONFIG3), 0.7, "fp64", 8),
-            ("721x241", dict(inputs.CONFIG4), 0.7, "fp32", 16),
-            ("721x241_F1.4", dict(inputs.CONFIG_F14), 1.4, "fp32", 16)]
+            ("361x121", dict(inputs.W361X121), 0.7, "fp64", 8),
+            ("721x241", dict(inputs.W721X241), 0.7, "fp32", 16),
+            ("721x241_F1.4", dict(inputs.W721X241_F14), 1.4, "fp32", 16)]
     for name, cfg, F, prec, q in runs:
         cfg = dict(cfg)
         cfg.pop("eps", None)
@@ -748,7 +751,7 @@ def precond_study():
         print(m, file=sys.stderr, flush=True)
 
     out = {"bandwidth_sweep": [], "spectra": {}}
-    cfg = dict(inputs.CONFIG3)
+    cfg = dict(inputs.W361X121)
     cfg.pop("eps")
     kw = dict(inputs.LARGE_SOLVE)
     u09, _, rec = _continue(api, cfg, 0.7, [round(0.1 * k, 1) for k in range(1, 10)], "fp64",
@@ -773,7 +776,7 @@ def precond_study():
         log(f"b={2 * q + 1}: {r}")
     # the same sweep on the finest mesh (spacing 0.075, half that of 361 x 121): cold FP64
     # solves of the benched workload (eps = 0.1 from the flat surface), set-up included
-    c4 = dict(inputs.CONFIG4)
+    c4 = dict(inputs.W721X241)
     out["bandwidth_sweep_721x241"] = []
     for q in (8, 12, 14, 16, 18, 20, 24):
         torch.cuda.synchronize()

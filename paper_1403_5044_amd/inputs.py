@@ -5,12 +5,12 @@ lives here.
 
 Workloads (meshes and domains; the paper's results section and Table 1 give
 the shapes this suite is modelled on):
-  config1  31 x 11   x in [-8, 8],   y in [0, 8],   eps 0.05, F 0.7
-  config2  181 x 61  x in [-16, 8],  y in [0, 12],  eps 0.1,  F 0.7
-  config3  361 x 121 x in [-14, 40], y in [0, 18],  F in {0.5, 0.7, 1.0}, eps in {0.1, 0.3}
-  config4  721 x 241 x in [-14, 40], y in [0, 18],  F 0.7, eps 0.1 .. 0.5
-  F = 1.4  721 x 241 x in [-56, 160], y in [0, 72],  eps 1 (spacing 0.3)
-  serving  meshes {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
+  W31X11    31 x 11   x in [-8, 8],   y in [0, 8],   eps 0.05, F 0.7
+  W181X61   181 x 61  x in [-16, 8],  y in [0, 12],  eps 0.1,  F 0.7
+  W361X121  361 x 121 x in [-14, 40], y in [0, 18],  F in {0.5, 0.7, 1.0}, eps in {0.1, 0.3}
+  W721X241  721 x 241 x in [-14, 40], y in [0, 18],  F 0.7, eps 0.1 .. 0.5
+  W721X241_F14  721 x 241 x in [-56, 160], y in [0, 72], F 1.4, eps 1 (spacing 0.3)
+  serving   meshes {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
            F ~ U[0.5, 1.0], eps ~ U[0.05, 0.4], Poisson arrivals
 """
 from __future__ import annotations
@@ -23,15 +23,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-CONFIG1 = dict(N=31, M=11, x1=-8.0, xN=8.0, yM=8.0, F=0.7, eps=0.05)
-CONFIG2 = dict(N=181, M=61, x1=-16.0, xN=8.0, yM=12.0, F=0.7, eps=0.1)
-CONFIG3 = dict(N=361, M=121, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
-CONFIG3_F = (0.5, 0.7, 1.0)
-CONFIG3_EPS = (0.1, 0.3)
-CONFIG4 = dict(N=721, M=241, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
-CONFIG4_EPS = (0.1, 0.2, 0.3, 0.4, 0.5)
+W31X11 = dict(N=31, M=11, x1=-8.0, xN=8.0, yM=8.0, F=0.7, eps=0.05)
+W181X61 = dict(N=181, M=61, x1=-16.0, xN=8.0, yM=12.0, F=0.7, eps=0.1)
+W361X121 = dict(N=361, M=121, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
+W361X121_F = (0.5, 0.7, 1.0)
+W361X121_EPS = (0.1, 0.3)
+W721X241 = dict(N=721, M=241, x1=-14.0, xN=40.0, yM=18.0, F=0.7, eps=0.1)
+W721X241_EPS = (0.1, 0.2, 0.3, 0.4, 0.5)
 # F = 1.4 on 721 x 241 with spacing 0.3 from x_1 = -56 (the paper's F = 1.4 surface)
-CONFIG_F14 = dict(N=721, M=241, x1=-56.0, xN=160.0, yM=72.0, F=1.4, eps=1.0)
+W721X241_F14 = dict(N=721, M=241, x1=-56.0, xN=160.0, yM=72.0, F=1.4, eps=1.0)
 # Block half-bandwidth of the preconditioner on the paper's domain: the band that
 # matters is a distance in y (1.2 here), so it doubles when the spacing halves
 Q_BLOCKS = {(361, 121): 8, (721, 241): 16}
@@ -77,21 +77,21 @@ def smooth_state(N: int, M: int, amp: float, seed: int) -> np.ndarray:
     return u
 
 
-def config2_linear_state() -> np.ndarray:
-    """The discrete linear solution at config 2 (eps = 0.1), written by
+def linear_state_181x61() -> np.ndarray:
+    """The discrete linear solution of the 181 x 61 workload (eps = 0.1), written by
     tests/golden/make_golden.py; its SHA-256 is checked on load."""
-    path = os.path.join(GOLDEN, "config2_linear_state.npy")
+    path = os.path.join(GOLDEN, "linear_state_181x61.npy")
     with open(path + ".sha256") as f:
         want = f.read().split()[0]
     raw = open(path, "rb").read()
     if hashlib.sha256(raw).hexdigest() != want:
-        raise RuntimeError("config2_linear_state.npy does not match its hash")
+        raise RuntimeError("linear_state_181x61.npy does not match its hash")
     return np.load(path, allow_pickle=False)
 
 
-def config2_batch(n: int = 16) -> list[np.ndarray]:
+def batch_181x61(n: int = 16) -> list[np.ndarray]:
     """The residual-throughput batch: linear solution + N(0, 1e-3 ** 2), seeds 0..n-1."""
-    base = config2_linear_state()
+    base = linear_state_181x61()
     return [perturbed(base, 1e-3, s) for s in range(n)]
 
 

@@ -1,14 +1,14 @@
 """Writes the stored inputs and expected values under tests/golden/ by calling
 only the oracle.
 
-config2_linear_state.npy: the root of the discrete linear system (the
+linear_state_181x61.npy: the root of the discrete linear system (the
 linearised problem of the paper's linear-problem section, discretised as in
 Appendix B) on the 181 x 61 mesh, x in [-16, 8], y in [0, 12], eps = 0.1,
 F = 0.7, i.e. u_flat - eps J_lin^{-1} s, solved through the Schur complement
 of Appendix C with all of D kept.  It seeds the residual-throughput batch
 (linear solution plus N(0, 1e-3^2) noise).
 
-config2_root.npy: the root of the nonlinear system E(u) = 0 on the same mesh
+root_181x61.npy: the root of the nonlinear system E(u) = 0 on the same mesh
 and parameters, by the oracle's damped Newton (exact complex-step JVPs, GMRES
 preconditioned by the full linear Jacobian) to ||E||_inf <= 1e-12, started
 from the linear solution (the eps-continuation path from the flat surface:
@@ -50,26 +50,26 @@ def _store(name, arr):
     return path, digest
 
 
-def config2():
+def problem_181x61():
     return Problem(181, 61, -16.0, 8.0, 12.0, F=0.7, eps=0.1)
 
 
 def make_linear():
     t = time.time()
-    u = linear_solution(config2())
-    path, digest = _store("config2_linear_state.npy", u)
+    u = linear_solution(problem_181x61())
+    path, digest = _store("linear_state_181x61.npy", u)
     print(f"wrote {path} ({u.size} values) in {time.time() - t:.1f} s, sha256 {digest}")
 
 
 def make_root():
     t = time.time()
-    prob = config2()
+    prob = problem_181x61()
     pre = BlockPreconditioner(prob, prob.M - 1)
     u0 = linear_solution(prob, pre)
     u, info = newton(prob, u0, tol=1e-12, pre=pre, eta=1e-6)
     if not info.converged:
         raise RuntimeError(f"oracle Newton did not converge: {info}")
-    path, digest = _store("config2_root.npy", u)
+    path, digest = _store("root_181x61.npy", u)
     print(f"wrote {path} in {time.time() - t:.1f} s: {info.newton} Newton, {info.gmres} GMRES, "
           f"norms {['%.2e' % v for v in info.norms]}, sha256 {digest}")
 

@@ -1,9 +1,9 @@
-"""Parity at the full shapes of configs 2-4 (181x61, 361x121 and 721x241), through the
+"""Parity at the full shapes of the 181x61, 361x121 and 721x241 workloads, through the
 C ABI, against the FP64 oracle.
 
-  * config 2: one state on every entry of E; the converged surface against the oracle's
+  * 181x61: one state on every entry of E; the converged surface against the oracle's
     own root (stored by tests/golden/make_golden.py with its SHA-256);
-  * configs 3 and 4: every E1/E4/E6 entry and 96 E2 entries (each a full sum over the
+  * 361x121 and 721x241: every E1/E4/E6 entry and 96 E2 entries (each a full sum over the
     grid) -- these meshes take the pair kernel's many-tile chunking;
   * the FP32-Kahan residual against the FP64 oracle on the same rows, against the bound
     stated below;
@@ -46,19 +46,19 @@ def _rows(p, n_e2, seed):
     return np.unique(np.concatenate([np.arange(NM), np.arange(NM, 2 * NM, p.N), e2, corners]))
 
 
-def test_config2_every_entry_fp64():
-    p = gprob(inputs.CONFIG2)
-    u = inputs.config2_batch(3)[2]
+def test_181x61_every_entry_fp64():
+    p = gprob(inputs.W181X61)
+    u = inputs.batch_181x61(3)[2]
     E = gpu_residual(p, u)
     op = oprob(p)
     Eo = oresidual(op, u)
     err = np.abs(E - Eo) / row_scale(op, u)
-    log(f"config2 all {E.size} entries: max rel err {err.max():.3e}")
+    log(f"181x61 all {E.size} entries: max rel err {err.max():.3e}")
     assert err.max() <= TOL64
 
 
-@pytest.mark.parametrize("name,cfg,amp", [("config3", inputs.CONFIG3, 0.02),
-                                          ("config4", inputs.CONFIG4, 0.02)])
+@pytest.mark.parametrize("name,cfg,amp", [("361x121", inputs.W361X121, 0.02),
+                                          ("721x241", inputs.W721X241, 0.02)])
 def test_large_mesh_residual_fp64_and_fp32(name, cfg, amp):
     p = gprob(cfg)
     op = oprob(p)
@@ -75,16 +75,16 @@ def test_large_mesh_residual_fp64_and_fp32(name, cfg, amp):
     assert e32 <= TOL32
 
 
-def test_config2_fp32_error_against_the_oracle():
-    p = gprob(inputs.CONFIG2)
+def test_181x61_fp32_error_against_the_oracle():
+    p = gprob(inputs.W181X61)
     op = oprob(p)
     worst = 0.0
-    for s, u in enumerate(inputs.config2_batch(4)):
+    for s, u in enumerate(inputs.batch_181x61(4)):
         rows = _rows(p, 48, 100 + s)
         Eo, sc = residual_rows(op, u, rows)
         E32 = gpu_residual(p.with_(precision="fp32"), u)[rows]
         worst = max(worst, (np.abs(E32 - Eo) / sc).max())
-    log(f"config2: FP32-Kahan max rel err vs oracle {worst:.3e} (bound {TOL32:.2e})")
+    log(f"181x61: FP32-Kahan max rel err vs oracle {worst:.3e} (bound {TOL32:.2e})")
     assert worst <= TOL32
 
 
@@ -102,28 +102,28 @@ def test_tall_mesh_spline_sweeps(N, M):
 
 
 def _golden_root():
-    path = os.path.join(GOLDEN, "config2_root.npy")
+    path = os.path.join(GOLDEN, "root_181x61.npy")
     want = open(path + ".sha256").read().split()[0]
     assert hashlib.sha256(open(path, "rb").read()).hexdigest() == want
     return np.load(path, allow_pickle=False)
 
 
-def test_config2_zeta_matches_the_oracle_root():
-    """The FP64 GPU solve of config 2 to ||E||_inf <= 1e-12 against the oracle's root
+def test_181x61_zeta_matches_the_oracle_root():
+    """The FP64 GPU solve of 181x61 to ||E||_inf <= 1e-12 against the oracle's root
     (converged to the same tolerance): zeta element by element within 1e-8; the mixed-
     precision solve within the stated 1e-6."""
-    p = gprob(inputs.CONFIG2)
+    p = gprob(inputs.W181X61)
     uo = _golden_root()
     zo = zeta_grid(oprob(p), uo).ravel()
     u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, tol=1e-12, max_newton=20)
-    log(f"config2 fp64 tol 1e-12: {info}")
+    log(f"181x61 fp64 tol 1e-12: {info}")
     assert info.status == 0
     dz = np.abs(host(z) - zo).max()
     du = np.abs(host(u) - uo).max()
-    log(f"config2 zeta vs oracle root {dz:.2e}; u {du:.2e}")
+    log(f"181x61 zeta vs oracle root {dz:.2e}; u {du:.2e}")
     assert dz <= 1e-8
     um, zm, im = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
                            tol=1e-10)
     dzm = np.abs(host(zm) - zo).max()
-    log(f"config2 mixed: {im}; zeta vs oracle root {dzm:.2e}")
+    log(f"181x61 mixed: {im}; zeta vs oracle root {dzm:.2e}")
     assert im.status == 0 and dzm <= 1e-6

@@ -1,4 +1,4 @@
-"""Configs 3 and 4 (361x121 and 721x241 on the paper's domain) on the GPU: the FP64
+"""361x121 and 721x241 on the paper's domain, on the GPU: the FP64
 root satisfies the oracle's E on sampled rows (every E1 row at a stride and E2 rows at
 random collocation points, each E2 row a full sum over the grid), and the mixed-precision
 root agrees with it within the stated bound."""
@@ -29,34 +29,34 @@ def _solve(cfg, F, eps, prec, P, u0=None):
                      precond=P, u0=u0, tol=1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
 
 
-def test_config3_root_satisfies_the_oracle_and_mixed_agrees():
-    cfg = dict(inputs.CONFIG3, F=1.0, eps=0.3)
+def test_361x121_root_satisfies_the_oracle_and_mixed_agrees():
+    cfg = dict(inputs.W361X121, F=1.0, eps=0.3)
     P = api.Preconditioner(api.Problem(**cfg), 8)
     u64, z64, i64 = _solve(cfg, 1.0, 0.3, "fp64", P)
     u32, z32, i32 = _solve(cfg, 1.0, 0.3, "fp32", P)
     P.close()
-    log(f"config3 F=1 eps=0.3 fp64 {i64}; mixed {i32}")
+    log(f"361x121 F=1 eps=0.3 fp64 {i64}; mixed {i32}")
     assert i64.status == 0 and i32.status == 0
-    err = _oracle_E_sampled(inputs.CONFIG3, 1.0, 0.3, u64, 7, 24)
+    err = _oracle_E_sampled(inputs.W361X121, 1.0, 0.3, u64, 7, 24)
     dz = np.abs(host(z64) - host(z32)).max()
-    log(f"config3: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
+    log(f"361x121: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
     assert err <= 1e-9
     assert dz <= 1e-6
     assert host(z64).max() <= cfg["F"] ** 2 / 2
 
 
-def test_config4_continuation_step_satisfies_the_oracle():
-    cfg = inputs.CONFIG4
+def test_721x241_continuation_step_satisfies_the_oracle():
+    cfg = inputs.W721X241
     P = api.Preconditioner(api.Problem(**cfg), inputs.Q_BLOCKS[(cfg["N"], cfg["M"])])
     um, zm, im = _solve(cfg, cfg["F"], 0.1, "fp32", P)
     assert im.status == 0
     u2, z2, i2 = _solve(cfg, cfg["F"], 0.2, "fp32", P, u0=um)
     u64, z64, i64 = _solve(cfg, cfg["F"], 0.2, "fp64", P, u0=um)
     P.close()
-    log(f"config4 eps=0.2 from eps=0.1: mixed {i2}; fp64 {i64}")
+    log(f"721x241 eps=0.2 from eps=0.1: mixed {i2}; fp64 {i64}")
     assert i2.status == 0 and i64.status == 0
     err = _oracle_E_sampled(cfg, cfg["F"], 0.2, u64, 97, 8)
     dz = np.abs(host(z64) - host(z2)).max()
-    log(f"config4: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
+    log(f"721x241: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
     assert err <= 1e-9
     assert dz <= 1e-6

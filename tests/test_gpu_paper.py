@@ -68,7 +68,7 @@ def test_eps1_root_on_91x31_matches_the_oracle_root():
 
 
 def test_eps1_root_on_361x121_satisfies_the_oracle():
-    cfg = dict(inputs.CONFIG3, eps=1.0)
+    cfg = dict(inputs.W361X121, eps=1.0)
     u, z, info = _continue(cfg, 8, 1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
     op = OProblem(cfg["N"], cfg["M"], cfg["x1"], cfg["xN"], cfg["yM"], F=cfg["F"], eps=1.0)
     NM = op.N * op.M

@@ -22,7 +22,7 @@ from gpu_common import dev, gprob, host, log, oprob
 
 pytestmark = pytest.mark.gpu
 
-C1 = inputs.CONFIG1
+C1 = inputs.W31X11
 ARGS1 = (C1["F"], C1["eps"], C1["N"], C1["M"], C1["x1"], C1["xN"], C1["yM"])
 
 

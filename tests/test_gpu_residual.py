@@ -21,7 +21,7 @@ TOL64 = 1e-11
 SMALL_CASES = [
     # (name, problem settings)
     ("tiny9x5", dict(N=9, M=5, x1=-3.0, xN=3.0, yM=2.0, F=0.7, eps=0.3)),
-    ("config1", inputs.CONFIG1),
+    ("31x11", inputs.W31X11),
     ("even40x9", dict(N=40, M=9, x1=-6.0, xN=5.0, yM=4.0, F=0.9, eps=0.2)),
     ("simpson13x7", dict(N=13, M=7, x1=-4.0, xN=4.0, yM=3.0, F=0.7, eps=0.4,
                          weights="simpson")),
@@ -42,7 +42,7 @@ def _check(name, p, u, E, tol=TOL64):
     return err.max()
 
 
-@pytest.mark.parametrize("name,cfg", [("config1", inputs.CONFIG1), ("config2", inputs.CONFIG2)])
+@pytest.mark.parametrize("name,cfg", [("31x11", inputs.W31X11), ("181x61", inputs.W181X61)])
 def test_flat_state_without_source_is_exactly_zero(name, cfg):
     p = gprob(cfg, eps=0.0)
     E = gpu_residual(p, inputs.flat_state(p.N, p.M))
@@ -61,17 +61,17 @@ def test_residual_parity_small_meshes(name, cfg):
         _check(f"{name}/state{seed}", p, u, E)
 
 
-def test_residual_parity_config2_batch_sampled():
-    """Config 2 (181 x 61), 16 states = linear solution + N(0, 1e-3^2): E1/E4/E6
+def test_residual_parity_181x61_batch_sampled():
+    """181 x 61, 16 states = linear solution + N(0, 1e-3^2): E1/E4/E6
     compared everywhere, E2 at 48 sampled collocation points per state (plus the
     corners of the collocation grid)."""
-    p = gprob(inputs.CONFIG2)
+    p = gprob(inputs.W181X61)
     op = oprob(p)
     NM = p.N * p.M
     rng = np.random.default_rng(123)
     corners = [NM + 1, NM + p.N - 1, NM + (p.M - 1) * p.N + 1, 2 * NM - 1]
     worst = 0.0
-    for s, u in enumerate(inputs.config2_batch(16)):
+    for s, u in enumerate(inputs.batch_181x61(16)):
         E = gpu_residual(p, u)
         assert np.all(np.isfinite(E))
         e2 = NM + rng.integers(0, p.M, 48) * p.N + rng.integers(1, p.N, 48)
@@ -81,18 +81,18 @@ def test_residual_parity_config2_batch_sampled():
         err = (np.abs(E[rows] - Eo) / sc).max()
         worst = max(worst, err)
         assert err <= TOL64, (s, err)
-    log(f"config2 batch: worst rel err {worst:.3e}")
+    log(f"181x61 batch: worst rel err {worst:.3e}")
 
 
 def test_residual_is_deterministic():
-    p = gprob(inputs.CONFIG2)
-    u = dev(inputs.config2_batch(1)[0])
+    p = gprob(inputs.W181X61)
+    u = dev(inputs.batch_181x61(1)[0])
     a = host(api.residual(p, u))
     b = host(api.residual(p, u))
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,cfg", [("config1", inputs.CONFIG1),
+@pytest.mark.parametrize("name,cfg", [("31x11", inputs.W31X11),
                                       ("ragged97x13", SMALL_CASES[5][1])])
 def test_fp32_kahan_residual_error_is_small(name, cfg):
     p = gprob(cfg)
@@ -106,7 +106,7 @@ def test_fp32_kahan_residual_error_is_small(name, cfg):
 
 
 def test_fp32_flat_state_without_source_is_exactly_zero():
-    p = gprob(inputs.CONFIG1, eps=0.0, precision="fp32")
+    p = gprob(inputs.W31X11, eps=0.0, precision="fp32")
     E = gpu_residual(p, inputs.flat_state(p.N, p.M))
     assert np.all(E == 0.0)
 
@@ -132,7 +132,7 @@ def test_jvp_matches_oracle_difference_quotient_and_exact_derivative():
     assert np.all(zero == 0.0)
 
 
-@pytest.mark.parametrize("cfg", [inputs.CONFIG1, inputs.CONFIG2,
+@pytest.mark.parametrize("cfg", [inputs.W31X11, inputs.W181X61,
                                  dict(N=130, M=7, x1=-10.0, xN=8.0, yM=3.0, F=0.8, eps=0.1)])
 def test_zeta_matches_trapezoid_integration(cfg):
     """One wavefront per row: 31 columns (one point per lane), 181 (three per lane) and
@@ -145,7 +145,7 @@ def test_zeta_matches_trapezoid_integration(cfg):
 
 
 def test_invalid_arguments_are_rejected():
-    p = gprob(inputs.CONFIG1)
+    p = gprob(inputs.W31X11)
     u = dev(inputs.flat_state(p.N, p.M))
     with pytest.raises(Exception):
         api.residual(p.with_(N=3), dev(inputs.flat_state(3, p.M)))

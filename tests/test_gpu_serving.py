@@ -18,7 +18,7 @@ DOM = inputs.SERVING_DOMAIN
 
 
 def test_batched_residual_is_bitwise_the_single_residual():
-    probs = [gprob(inputs.CONFIG1),
+    probs = [gprob(inputs.W31X11),
              api.Problem(61, 21, **DOM, F=0.6, eps=0.2, precision="fp32"),
              api.Problem(121, 41, **DOM, F=0.9, eps=0.3),
              api.Problem(9, 5, -3.0, 3.0, 2.0, F=0.7, eps=0.3),
@@ -101,3 +101,41 @@ def test_server_admission_by_memory_budget():
 def test_server_rejects_invalid_requests():
     res = _serve([(0.7, 0.1, 3, 11, -8.0, 8.0, 8.0), REQS[0]], precision="fp64")
     assert res[0].status == -1 and res[1].status == 0
+
+
+def test_server_large_serving_meshes_satisfy_the_oracle():
+    """The two larger serving meshes (181x61 and 241x81, the server's q = 5 and 8) in one
+    mix with the smaller ones: every result converges, mixed precision agrees with FP64
+    within 1e-6, and the FP64 roots satisfy the oracle's E on sampled rows to 1e-9 (each
+    E2 row a full sum over the grid)."""
+    from oracle import Problem as OProblem
+    from oracle.equations import residual_rows
+    reqs = [(0.65, 0.25, 241, 81, *DOM.values()),
+            (0.85, 0.15, 181, 61, *DOM.values()),
+            (0.75, 0.35, 121, 41, *DOM.values()),
+            (0.95, 0.1, 61, 21, *DOM.values())]
+    r64 = _serve(reqs, precision="fp64", max_slots=8, hbm_budget_bytes=64e9)
+    r32 = _serve(reqs, precision="fp32", max_slots=8, hbm_budget_bytes=64e9)
+    rng = np.random.default_rng(3)
+    for a, b, (F, eps, N, M, x1, xN, yM) in zip(r64, r32, reqs):
+        assert a.status == 0 and b.status == 0
+        dz = np.abs(a.zeta - b.zeta).max()
+        log(f"server {N}x{M} F={F} eps={eps}: fp64 newton {a.newton_iters} gmres "
+            f"{a.gmres_iters}; mixed vs fp64 zeta {dz:.2e}")
+        assert dz <= 1e-6
+        # the server returns zeta; the state comes from a direct solve of the same request
+        # (tol 1e-12), whose zeta must agree with the server's (tol 1e-10) to within
+        # 1e-7, a thousand times the server's residual tolerance
+        u, z, info = api.solve(F, eps, N, M, x1, xN, yM, tol=1e-12, max_gmres=600,
+                               gmres_restart=60)
+        assert info.status == 0
+        dd = np.abs(host(z) - a.zeta).max()
+        log(f"  server vs direct solve zeta {dd:.2e}")
+        assert dd <= 1e-7
+        op = OProblem(N, M, x1, xN, yM, F=F, eps=eps)
+        NM = N * M
+        e2 = NM + rng.integers(0, M, 8) * N + rng.integers(1, N, 8)
+        rows = np.unique(np.concatenate([np.arange(0, NM, 13), e2]))
+        E, _ = residual_rows(op, host(u), rows)
+        log(f"  oracle |E| at the direct solve's root on {rows.size} rows: {np.abs(E).max():.2e}")
+        assert np.abs(E).max() <= 1e-9

@@ -24,7 +24,7 @@ def _backward_error(P, x, b):
 SMALL = dict(N=15, M=7, x1=-6.0, xN=6.0, yM=5.0, F=0.7, eps=0.05)
 
 
-@pytest.mark.parametrize("cfg", [TINY, SMALL, inputs.CONFIG1,
+@pytest.mark.parametrize("cfg", [TINY, SMALL, inputs.W31X11,
                                  dict(N=41, M=13, x1=-8.0, xN=8.0, yM=6.0, F=0.9, eps=0.1,
                                       weights="simpson")])
 def test_preconditioner_apply_matches_dense_solve(cfg):
@@ -47,7 +47,7 @@ def test_preconditioner_apply_matches_dense_solve(cfg):
 
 
 def test_preconditioner_apply_in_place():
-    p = gprob(inputs.CONFIG1)
+    p = gprob(inputs.W31X11)
     b = np.random.default_rng(1).standard_normal(p.n_unknowns)
     P = api.Preconditioner(p, 1)
     x1 = host(P.apply(dev(b)))
@@ -65,11 +65,11 @@ def _oracle_root(p, tol=1e-12):
 
 
 @pytest.mark.parametrize("q", [0, 1, 10])
-def test_config1_fp64_solve_matches_oracle_root(q):
-    p = gprob(inputs.CONFIG1)
+def test_31x11_fp64_solve_matches_oracle_root(q):
+    p = gprob(inputs.W31X11)
     uo = _oracle_root(p)
     u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, q_blocks=q, tol=1e-11)
-    log(f"config1 q={q}: {info}")
+    log(f"31x11 q={q}: {info}")
     assert info.status == 0
     ug = host(u)
     zg = host(z)
@@ -80,21 +80,21 @@ def test_config1_fp64_solve_matches_oracle_root(q):
     assert zg.max() <= p.F ** 2 / 2
 
 
-def test_config1_mixed_precision_solve_within_stated_bound():
-    p = gprob(inputs.CONFIG1)
+def test_31x11_mixed_precision_solve_within_stated_bound():
+    p = gprob(inputs.W31X11)
     uo = _oracle_root(p)
     u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
                            tol=1e-10)
-    log(f"config1 mixed: {info}")
+    log(f"31x11 mixed: {info}")
     assert info.status == 0
     zo = zeta_grid(oprob(p), uo).ravel()
     err = np.abs(host(z) - zo).max()
-    log(f"config1 mixed zeta err {err:.2e}")
+    log(f"31x11 mixed zeta err {err:.2e}")
     assert err <= 1e-6
 
 
 def test_solve_continuation_from_caller_state():
-    p = gprob(inputs.CONFIG1)
+    p = gprob(inputs.W31X11)
     u, _, info = api.solve(p.F, 0.05, p.N, p.M, p.x1, p.xN, p.yM)
     assert info.status == 0
     u2, z2, info2 = api.solve(p.F, 0.1, p.N, p.M, p.x1, p.xN, p.yM, u0=u)
@@ -104,12 +104,12 @@ def test_solve_continuation_from_caller_state():
     assert np.abs(host(z2) - zo).max() <= 1e-8
 
 
-def test_config2_solve_is_a_root_of_the_oracle_system():
-    """Config 2 (181 x 61, eps 0.1): the GPU root, checked by the oracle on
+def test_181x61_solve_is_a_root_of_the_oracle_system():
+    """181 x 61, eps 0.1: the GPU root, checked by the oracle on
     every E1/E4/E6 entry and on sampled E2 entries; FP32-mixed root agrees."""
-    p = gprob(inputs.CONFIG2)
+    p = gprob(inputs.W181X61)
     u, z, info = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, tol=1e-10)
-    log(f"config2 fp64: {info}")
+    log(f"181x61 fp64: {info}")
     assert info.status == 0
     ug = host(u)
     op = oprob(p)
@@ -118,16 +118,16 @@ def test_config2_solve_is_a_root_of_the_oracle_system():
     e2 = NM + rng.integers(0, p.M, 40) * p.N + rng.integers(1, p.N, 40)
     rows = np.unique(np.concatenate([np.arange(NM), e2]))
     Eo, _ = residual_rows(op, ug, rows)
-    log(f"config2 oracle |E(u_gpu)| max {np.abs(Eo).max():.2e}")
+    log(f"181x61 oracle |E(u_gpu)| max {np.abs(Eo).max():.2e}")
     assert np.abs(Eo).max() <= 1e-9
     zg = host(z)
     assert zg.max() <= p.F ** 2 / 2
     um, zm, infom = api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM, precision="fp32",
                               tol=1e-10)
-    log(f"config2 mixed: {infom}")
+    log(f"181x61 mixed: {infom}")
     assert infom.status == 0
     err = np.abs(host(zm) - zg).max()
-    log(f"config2 mixed vs fp64 zeta {err:.2e}")
+    log(f"181x61 mixed vs fp64 zeta {err:.2e}")
     assert err <= 1e-6
 
 
@@ -200,7 +200,7 @@ def test_preconditioner_band_orders_match_dense_solve(N, M, q):
     P.close()
 
 
-@pytest.mark.parametrize("cfg,q", [(inputs.CONFIG2, 5), (dict(N=241, M=21, x1=-16.0, xN=8.0,
+@pytest.mark.parametrize("cfg,q", [(inputs.W181X61, 5), (dict(N=241, M=21, x1=-16.0, xN=8.0,
                                                               yM=12.0, F=0.8, eps=0.2), 8)])
 def test_cold_solve_equals_prebuilt_preconditioner_bitwise(cfg, q):
     """A cold solve builds its preconditioner on a helper stream beside the first residual

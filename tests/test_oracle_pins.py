@@ -329,7 +329,7 @@ def test_dense_newton_is_quadratic_and_agrees_with_jfnk():
     assert np.abs(ud - uj).max() <= 1e-10
 
 
-def test_config1_root_satisfies_invariants():
+def test_31x11_root_satisfies_invariants():
     u, info = newton(C1, flat_state(C1), tol=1e-12)
     assert info.converged
     parts = R.residual_parts(C1, u)

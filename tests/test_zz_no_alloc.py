@@ -27,8 +27,8 @@ def _pair(p, u):
 
 
 def test_noalloc_matches_the_allocating_entry_point_twice_then_smaller():
-    cases = [(gprob(inputs.CONFIG2), inputs.config2_batch(2)[1]),
-             (gprob(inputs.CONFIG1), inputs.smooth_state(31, 11, 0.05, 3))]
+    cases = [(gprob(inputs.W181X61), inputs.batch_181x61(2)[1]),
+             (gprob(inputs.W31X11), inputs.smooth_state(31, 11, 0.05, 3))]
     for p, u in cases:
         ref, got = _pair(p, u)
         sc = row_scale(oprob(p), u)
@@ -41,8 +41,8 @@ def test_noalloc_matches_the_allocating_entry_point_twice_then_smaller():
 
 
 def test_noalloc_fp32_and_repeat():
-    p = gprob(inputs.CONFIG2, precision="fp32")
-    u = inputs.config2_batch(1)[0]
+    p = gprob(inputs.W181X61, precision="fp32")
+    u = inputs.batch_181x61(1)[0]
     ref, got = _pair(p, u)
     sc = row_scale(oprob(p), u)
     err = (np.abs(got - ref) / sc).max()

@@ -29,20 +29,25 @@ def _solve(cfg, F, eps, prec, P, u0=None):
                      precond=P, u0=u0, tol=1e-10, max_gmres=600, gmres_restart=60, max_newton=20)
 
 
-def test_361x121_root_satisfies_the_oracle_and_mixed_agrees():
-    cfg = dict(inputs.W361X121, F=1.0, eps=0.3)
-    P = api.Preconditioner(api.Problem(**cfg), 8)
-    u64, z64, i64 = _solve(cfg, 1.0, 0.3, "fp64", P)
-    u32, z32, i32 = _solve(cfg, 1.0, 0.3, "fp32", P)
+@pytest.mark.parametrize("F", inputs.W361X121_F)
+def test_361x121_roots_satisfy_the_oracle_and_mixed_agrees(F):
+    """Every point of the 361x121 F x eps grid (one preconditioner per F, q = 8): the FP64
+    root satisfies the oracle's E on sampled rows, the mixed-precision root agrees with
+    it within 1e-6, and zeta stays below the Bernoulli bound F^2 / 2."""
+    cfg = dict(inputs.W361X121, F=F)
+    P = api.Preconditioner(api.Problem(**cfg), inputs.Q_BLOCKS[(cfg["N"], cfg["M"])])
+    for eps in inputs.W361X121_EPS:
+        u64, z64, i64 = _solve(cfg, F, eps, "fp64", P)
+        u32, z32, i32 = _solve(cfg, F, eps, "fp32", P)
+        log(f"361x121 F={F} eps={eps} fp64 {i64}; mixed {i32}")
+        assert i64.status == 0 and i32.status == 0
+        err = _oracle_E_sampled(inputs.W361X121, F, eps, u64, 7, 24)
+        dz = np.abs(host(z64) - host(z32)).max()
+        log(f"  oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
+        assert err <= 1e-9
+        assert dz <= 1e-6
+        assert host(z64).max() <= F ** 2 / 2
     P.close()
-    log(f"361x121 F=1 eps=0.3 fp64 {i64}; mixed {i32}")
-    assert i64.status == 0 and i32.status == 0
-    err = _oracle_E_sampled(inputs.W361X121, 1.0, 0.3, u64, 7, 24)
-    dz = np.abs(host(z64) - host(z32)).max()
-    log(f"361x121: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
-    assert err <= 1e-9
-    assert dz <= 1e-6
-    assert host(z64).max() <= cfg["F"] ** 2 / 2
 
 
 def test_721x241_continuation_step_satisfies_the_oracle():
@@ -60,3 +65,29 @@ def test_721x241_continuation_step_satisfies_the_oracle():
     log(f"721x241: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}")
     assert err <= 1e-9
     assert dz <= 1e-6
+
+
+def test_721x241_eps1_by_continuation_satisfies_the_oracle():
+    """The paper's eps = 1 surface on 721 x 241 (F = 0.7): continuation in steps of 0.1 in
+    mixed precision, and the last step again in FP64 from the eps = 0.9 root; the FP64 root
+    satisfies the oracle's E on sampled rows (every 97th E1/E4/E6 row and 8 E2 rows, each a
+    sum over all 173,761 grid points) and agrees with the mixed root within 1e-6."""
+    cfg = inputs.W721X241
+    P = api.Preconditioner(api.Problem(**cfg), inputs.Q_BLOCKS[(cfg["N"], cfg["M"])])
+    u, u_prev = None, None
+    for k in range(1, 11):
+        un, zm, im = _solve(cfg, cfg["F"], 0.1 * k, "fp32", P, u0=u)
+        assert im.status == 0, f"continuation stopped at eps {0.1 * k}"
+        u_prev, u = u, un
+    # the FP64 solve takes the last continuation step itself, from the eps = 0.9 root
+    u64, z64, i64 = _solve(cfg, cfg["F"], 1.0, "fp64", P, u0=u_prev)
+    P.close()
+    log(f"721x241 eps=1: mixed {im}; fp64 {i64}")
+    assert i64.status == 0
+    err = _oracle_E_sampled(cfg, cfg["F"], 1.0, u64, 97, 8)
+    dz = np.abs(host(z64) - host(zm)).max()
+    log(f"721x241 eps=1: oracle |E| on sampled rows {err:.2e}; mixed vs fp64 zeta {dz:.2e}; "
+        f"max zeta {host(z64).max():.4f}")
+    assert err <= 1e-9
+    assert dz <= 1e-6
+    assert host(z64).max() <= cfg["F"] ** 2 / 2

@@ -397,6 +397,16 @@ def extra_measurements(api, inputs, cfg, one_solve, z64, args):
                           "newton": infom.newton_iters, "gmres": infom.gmres_iters,
                           "evals": infom.residual_evals, "final_norm": infom.final_norm,
                           "zeta_vs_fp64_solve": (zm - z64).abs().max().item()}
+    # the same FP64 solve from the linear-solution initial guess (u_flat - eps P^-1 s with
+    # the solve's own preconditioner) instead of the flat surface
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, zl, infol = one_solve(init="linear")
+    torch.cuda.synchronize()
+    res["linear_init_solve"] = {"s": time.perf_counter() - t0, "status": infol.status,
+                                "newton": infol.newton_iters, "gmres": infol.gmres_iters,
+                                "evals": infol.residual_evals,
+                                "zeta_vs_flat_start": (zl - z64).abs().max().item()}
     err = fp32_error_vs_oracle(api, cfg, um)
     err["solve_estimate"] = infom.fp32_error
     err["what"] = ("FP32-Kahan residual at the mixed-precision root against the FP64 oracle "

@@ -442,6 +442,8 @@ def serving_runs(api, inputs, nreq):
     import numpy as np
     dom = inputs.SERVING_DOMAIN
 
+    dump = [] if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+
     def run(srv, reqs, rate=None):
         t0 = time.perf_counter()
         tickets = []
@@ -456,6 +458,11 @@ def serving_runs(api, inputs, nreq):
         res = [srv.poll(t) for t in tickets]
         lat = np.array([r.t_done_s - r.t_submit_s for r in res])
         ok = sum(1 for r in res if r.status == 0)
+        if dump is not None:
+            dump.append([{"N": q[1], "M": q[2], "F": q[3], "eps": q[4], "status": r.status,
+                          "wait_s": r.t_admit_s - r.t_submit_s,
+                          "service_s": r.t_done_s - r.t_admit_s, "newton": r.newton_iters,
+                          "gmres": r.gmres_iters} for q, r in zip(reqs, res)])
         errs = [r.fp32_error for r in res if r.fp32_error >= 0]
         return {"requests": len(res), "converged": ok,
                 "fallbacks": sum(r.used_fallback for r in res),
@@ -484,6 +491,9 @@ def serving_runs(api, inputs, nreq):
         servers[prec].close()
         print(f"serving poisson {prec}: {out[f'poisson_{prec}']}", file=sys.stderr, flush=True)
     out["arrival_rate_per_s"] = rate
+    if dump is not None:
+        with open(os.path.join(ROOT, "gpurun_out", "serving_requests.json"), "w") as f:
+            json.dump(dump, f)
     out["workload"] = (f"serving: {nreq} requests, Poisson arrivals at {rate:.2f}/s (80% of "
                        f"closed-loop mixed capacity), meshes 61x21/121x41/181x61/241x81 on "
                        f"[-16, 8]x[0, 12], F~U[0.5,1], eps~U[0.05,0.4], seed 0, q by mesh "

@@ -1081,7 +1081,145 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
             }
 }
 
+// The Schur update of one eliminated block row l as a single product: with nbr the nn
+// rows coupled to l, C(a, b) += alpha A_a G_b for a, b < nn, where A_a = S(nbr[a], l),
+// G_b the b-th block of G and C(a, b) = S(nbr[a], nbr[b]).  The (nn N) x (nn N) x N
+// product is tiled as one matrix whose rows run over (a, i) and columns over (b, j), so
+// only its last tile row and column are padded, where a 721^3 block product alone pads
+// 721 to 768 in both dimensions (13% of its matrix-core work).  A pair that is not in
+// the mask is neither updated nor, where a whole tile lies in such pairs, computed.
+constexpr int kMaxRowNbr = 32;
+struct RowProd {
+    const double* A[kMaxRowNbr];  // A_a, N x N row-major
+    double* Crow[kMaxRowNbr];     // C(a, b) = Crow[a] + b N^2
+    const double* G;              // G_b = G + b N^2
+    unsigned mask[kMaxRowNbr];    // bit b of word a: pair (a, b) is updated
+    int nn;
+};
+struct RowProdArgs {
+    RowProd p[2];
+    int tiles0;  // tiles of problem 0; the rest of the grid is problem 1
+};
 
+// 64 x 64 tile per 256-thread workgroup, 2 x 2 wavefronts of 2 x 2 v_mfma_f64_16x16x4f64
+// tiles, K in slices of 16 double-buffered in LDS through a register prefetch (one
+// barrier per slice).  Loads are unconditional: rows and columns past the product are
+// read clamped (they reach only outputs that are not stored) and the K padding is zeroed
+// on B's side with a bit mask, so that no load waits on a branch.  Tiles are taken
+// eight tile rows at a time, column by column, and consecutive tiles stay on one XCD.
+// Each element's K sum runs in the same order as in k_gemm, so the two give the same
+// bits.
+__global__ __launch_bounds__(256) void k_schur_rows(int N, double alpha, RowProdArgs args) {
+    constexpr int T = 64, KS = 16, RA = 4, RB = 4, AR = 16, BKP = 4, kGroup = 8;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int pi = lin < args.tiles0 ? 0 : 1;
+    const RowProd& P = args.p[pi];
+    const int tile = lin - (pi ? args.tiles0 : 0);
+    const int nt = P.nn * N;
+    const int tpd = (nt + T - 1) / T;
+    const int grp = tile / (kGroup * tpd);
+    const int gsz = min(kGroup, tpd - grp * kGroup);
+    const int within = tile - grp * kGroup * tpd;
+    const int row0 = (grp * kGroup + within % gsz) * T, col0 = (within / gsz) * T;
+    {
+        const int a0 = row0 / N, a1 = (min(row0 + T, nt) - 1) / N;
+        const int b0 = col0 / N, b1 = (min(col0 + T, nt) - 1) / N;
+        unsigned any = 0;
+        for (int a = a0; a <= a1; ++a) any |= P.mask[a] >> b0 & ((2u << (b1 - b0)) - 1u);
+        if (!any) return;
+    }
+    __shared__ double As[2][T][KS + 1];
+    __shared__ double Bs[2][KS][T + 2];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // A slice T x 16: thread t takes k = t % 16 of rows t / 16 + 16 e; B slice 16 x T:
+    // column t % T of k-rows t / T + 4 e
+    const int ak = t % KS, ar = t / KS;
+    const double* arow[RA];
+#pragma unroll
+    for (int e = 0; e < RA; ++e) {
+        const int r = min(row0 + ar + AR * e, nt - 1);
+        const int a = r / N;
+        arow[e] = P.A[a] + (size_t)(r - a * N) * N;
+    }
+    const int bcl = t % T, bk0 = t / T;
+    const double* bcolp;
+    {
+        const int c = min(col0 + bcl, nt - 1);
+        const int b = c / N;
+        bcolp = P.G + (size_t)b * N * N + (c - b * N);
+    }
+    double ra[RA], rb[RB];
+    unsigned bmask[RB];
+    auto load = [&](int k0) {
+        const int gk = min(k0 + ak, N - 1);
+#pragma unroll
+        for (int e = 0; e < RA; ++e) ra[e] = arow[e][gk];
+#pragma unroll
+        for (int e = 0; e < RB; ++e) {
+            const int gkb = k0 + bk0 + BKP * e;
+            bmask[e] = (gkb < N) ? ~0u : 0u;
+            rb[e] = bcolp[(size_t)min(gkb, N - 1) * N];
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < RA; ++e) As[buf][ar + AR * e][ak] = ra[e];
+#pragma unroll
+        for (int e = 0; e < RB; ++e) {
+            const unsigned long long m = ((unsigned long long)bmask[e] << 32) | bmask[e];
+            Bs[buf][bk0 + BKP * e][bcl] =
+                __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, rb[e]) & m);
+        }
+    };
+    const int ns = (N + KS - 1) / KS;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+        const int buf = s & 1;
+        const int k0 = s * KS;
+        if (s + 1 < ns) load(k0 + KS);
+#pragma unroll
+        for (int k4 = 0; k4 < KS; k4 += 4) {
+            if (k0 + k4 < N) {
+                double fa[2], fb[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) fa[a] = As[buf][wr + a * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) fb[b] = Bs[buf][k4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            }
+        }
+        if (s + 1 < ns) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int c = col0 + wc + b * 16 + (lane & 15);
+        const int bb = c / N, j = c - bb * N;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = row0 + wr + a * 16 + (lane >> 4) + 4 * r;
+                const int aa = rr / N, i = rr - aa * N;
+                if (rr < nt && c < nt && ((P.mask[aa] >> bb) & 1u)) {
+                    double* o = P.Crow[aa] + (size_t)bb * N * N + (size_t)i * N + j;
+                    *o = *o + alpha * acc[a][b][r];
+                }
+            }
+    }
+}
 
 // Small blocks (N <= 256): one 32 x 32 output tile per 256-thread workgroup.  The four
 // wavefronts take interleaved quarters of K (wavefront w: k-steps of 4 numbered w, w + 4,
@@ -1484,6 +1622,24 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
     }
 }
 
+// Row products (k_schur_rows) of up to two eliminated rows in one launch; problems whose
+// mask is empty are dropped.
+void schur_rows(int N, double alpha, const RowProd* rp, int np, hipStream_t s) {
+    RowProdArgs args{};
+    int tiles[2] = {0, 0}, k = 0;
+    for (int i = 0; i < np; ++i) {
+        unsigned any = 0;
+        for (int a = 0; a < rp[i].nn; ++a) any |= rp[i].mask[a];
+        if (!any) continue;
+        args.p[k] = rp[i];
+        const int tpd = (rp[i].nn * N + 63) / 64;
+        tiles[k++] = tpd * tpd;
+    }
+    if (k == 0) return;
+    args.tiles0 = tiles[0];
+    k_schur_rows<<<tiles[0] + tiles[1], 256, 0, s>>>(N, alpha, args);
+}
+
 
 }  // namespace
 
@@ -1709,6 +1865,11 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
         std::vector<GemmJob> jobs1 = pendingL, diag_a, diag_b, rest_a, rest_b;
         pendingL.clear();
         std::vector<const double*> top_targets;
+        // with N > 256 and consecutive coupled rows, a row's Schur updates outside the
+        // diagonal launches run as one row product (rp_rest, and rp_late for the bottom
+        // updates that must wait for the top chain's)
+        RowProd rp_rest[2], rp_late[2];
+        int nrp = 0;
         for (int e = 0; e < nr; ++e) {
             const int l = rows[e];
             const int ch = (step < ns && l >= o.k) ? 1 : 0;
@@ -1724,6 +1885,27 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
             for (int b = 0; b < nn; ++b)
                 jobs1.push_back(
                     GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
+            // the product addresses C(a, b) as C(a, 0) + b N^2: the coupled rows must be
+            // consecutive band rows
+            bool consecutive = g.N > 256 && nn <= kMaxRowNbr;
+            for (int a = 0; a < nn && consecutive; ++a)
+                for (int b = 0; b < nn && consecutive; ++b)
+                    consecutive = Sb(nbr[a], nbr[b]) == Sb(nbr[a], nbr[0]) + (size_t)b * NN;
+            RowProd* rr = nullptr;
+            RowProd* rl = nullptr;
+            if (consecutive) {
+                rr = &rp_rest[nrp];
+                rl = &rp_late[nrp];
+                ++nrp;
+                *rr = RowProd{};
+                rr->G = sc + (size_t)q * NN;
+                rr->nn = nn;
+                for (int a = 0; a < nn; ++a) {
+                    rr->A[a] = Sb(nbr[a], l);
+                    rr->Crow[a] = Sb(nbr[a], nbr[0]);
+                }
+                *rl = *rr;
+            }
             for (int a = 0; a < nn; ++a)
                 for (int b = 0; b < nn; ++b) {
                     double* Sij = Sb(nbr[a], nbr[b]);
@@ -1733,7 +1915,11 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
                     bool diag = false;
                     for (int x = 0; x < nnext; ++x) diag = diag || Sij == Sb(next[x], next[x]);
                     if (!s2) diag = false;  // one stream: everything in the rest launches
-                    (diag ? (late ? diag_b : diag_a) : (late ? rest_b : rest_a)).push_back(j);
+                    if (!diag && rr) {
+                        (late ? rl : rr)->mask[a] |= 1u << b;
+                    } else {
+                        (diag ? (late ? diag_b : diag_a) : (late ? rest_b : rest_a)).push_back(j);
+                    }
                     if (ch == 0) top_targets.push_back(Sij);
                 }
             for (int b = 0; b < nn; ++b)
@@ -1744,7 +1930,7 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
         }
         if (!jobs1.empty()) gemm_batched(g.N, 1.0, jobs1, s);
         hipStream_t rs = s;
-        if (s2 && (!rest_a.empty() || !rest_b.empty())) {
+        if (s2 && (!rest_a.empty() || !rest_b.empty() || nrp > 0)) {
             hipEvent_t e = new_event();
             SW_HIP(hipEventRecord(e, s));
             SW_HIP(hipStreamWaitEvent(s2, e, 0));
@@ -1752,7 +1938,9 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
         }
         if (!diag_a.empty()) gemm_batched(g.N, -1.0, diag_a, s);
         if (!diag_b.empty()) gemm_batched(g.N, -1.0, diag_b, s);
+        schur_rows(g.N, -1.0, rp_rest, nrp, rs);
         if (!rest_a.empty()) gemm_batched(g.N, -1.0, rest_a, rs);
+        schur_rows(g.N, -1.0, rp_late, nrp, rs);
         if (!rest_b.empty()) gemm_batched(g.N, -1.0, rest_b, rs);
         if (rs != s) {
             side_done = new_event();

@@ -181,12 +181,16 @@ def test_preconditioner_wide_blocks_match_dense_solve(N, M):
 
 
 @pytest.mark.parametrize("N,M,q", [(31, 40, 8), (31, 60, 10), (15, 20, 19), (41, 13, 6),
-                                   (41, 14, 3), (21, 9, 2)])
+                                   (41, 14, 3), (21, 9, 2), (300, 14, 4), (700, 9, 2)])
 def test_preconditioner_band_orders_match_dense_solve(N, M, q):
     """The band is eliminated from both ends with q separator rows last.  Cases: a top and
     a bottom super row too large to share a launch (31 x 40, q = 8), a separator super row
     that has to shrink to fit (31 x 60, q = 10), q = M - 1 (no bottom chain), and M - q
-    odd and even (chains of equal and unequal length)."""
+    odd and even (chains of equal and unequal length).  With N > 256 each eliminated
+    row's Schur updates run as one row product: at 300 x 14 (q = 4) and 700 x 9 (q = 2)
+    the chains meet, so the products leave out the next diagonal blocks and the bottom
+    updates that wait for the top chain's, which run in launches of their own; 700 also
+    substitutes one block row per step."""
     p = api.Problem(N, M, -10.0, 8.0, 3.0, F=0.75, eps=0.1)
     op = oprob(p)
     Pm = OL.BlockPreconditioner(op, q).matrix()

@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="serving workload: Poisson arrivals of mixed solves (prints its own line)")
     ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--serving-rate", type=float, default=None,
+                    help="Poisson arrival rate of --serving (default: 80%% of the closed-loop "
+                         "mixed capacity)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--residuals", action="store_true",
@@ -431,7 +434,7 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "dispatches": 3}))
 
 
-def serving_runs(api, inputs, nreq):
+def serving_runs(api, inputs, nreq, fixed_rate=None):
     """Serving workload: requests with Poisson arrivals, meshes uniform over
     {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
     F ~ U[0.5, 1.0], eps ~ U[0.05, 0.4] (seed 0).  First a closed-loop run
@@ -484,7 +487,7 @@ def serving_runs(api, inputs, nreq):
         print(f"serving closed loop {prec}: {out[f'closed_loop_{prec}']}", file=sys.stderr,
               flush=True)
     capacity = out["closed_loop_fp32"]["solves_per_s"]
-    rate = 0.8 * capacity
+    rate = fixed_rate if fixed_rate else 0.8 * capacity
     reqs = inputs.serving_requests(nreq, rate, 0)
     for prec in ("fp32", "fp64"):
         out[f"poisson_{prec}"] = run(servers[prec], reqs, rate=rate)
@@ -494,8 +497,9 @@ def serving_runs(api, inputs, nreq):
     if dump is not None:
         with open(os.path.join(ROOT, "gpurun_out", "serving_requests.json"), "w") as f:
             json.dump(dump, f)
-    out["workload"] = (f"serving: {nreq} requests, Poisson arrivals at {rate:.2f}/s (80% of "
-                       f"closed-loop mixed capacity), meshes 61x21/121x41/181x61/241x81 on "
+    how = "fixed" if fixed_rate else "80% of closed-loop mixed capacity"
+    out["workload"] = (f"serving: {nreq} requests, Poisson arrivals at {rate:.2f}/s ({how}), "
+                       f"meshes 61x21/121x41/181x61/241x81 on "
                        f"[-16, 8]x[0, 12], F~U[0.5,1], eps~U[0.05,0.4], seed 0, q by mesh "
                        f"(5 for N <= 200, 8 beyond)")
     return out
@@ -505,7 +509,7 @@ def serving(args):
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
     _lib.load()
-    out = serving_runs(api, inputs, args.requests)
+    out = serving_runs(api, inputs, args.requests, args.serving_rate)
     line = {"metric": METRIC,
             "value": out["poisson_fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
             "steps": args.requests, "warmup": args.requests, "higher_is_better": True,

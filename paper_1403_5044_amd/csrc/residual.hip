@@ -37,12 +37,11 @@ constexpr int kMaxDenseSplineM = 512;
 
 // ---- a1-a2: trapezoid integration in x, radiation rows -------------------------
 // One wavefront per (row l, field f): f = 0 -> psi from phi_x - 1, f = 1 -> zeta.
-__global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ u,
-                                             double* __restrict__ psi,
-                                             double* __restrict__ zeta,
-                                             double* __restrict__ E) {
-    const int l = blockIdx.x;
-    const int f = blockIdx.y;
+// The bodies of this and the other prelude and finish kernels take their block index
+// as arguments, so that the batched launches below run them unchanged.
+__device__ __forceinline__ void scan_body(const Geo& g, const double* __restrict__ u,
+                                          double* __restrict__ psi, double* __restrict__ zeta,
+                                          double* __restrict__ E, int l, int f) {
     const int lane = threadIdx.x;
     const int N = g.N;
     const double* in = u + (size_t)f * g.NM + (size_t)l * N;
@@ -73,6 +72,13 @@ __global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ u
         const double fx1 = in[1] - off;
         E[(size_t)f * g.NM + (size_t)l * N] = g.x1 * (fx1 - fx0) / g.dx + g.nu * fx0;
     }
+}
+
+__global__ __launch_bounds__(64) void k_scan(Geo g, const double* __restrict__ u,
+                                             double* __restrict__ psi,
+                                             double* __restrict__ zeta,
+                                             double* __restrict__ E) {
+    scan_body(g, u, psi, zeta, E, blockIdx.x, blockIdx.y);
 }
 
 // ---- a3: cubic-spline slopes in y ----------------------------------------------------
@@ -179,14 +185,13 @@ __global__ void k_spline_operator(int M, int bc, double* __restrict__ Q) {
 }
 
 // psi_y, zeta_y = (1/h) Q f for every column at once: block (x-tile, row j, field).
-__global__ __launch_bounds__(128) void k_spline_dense(Geo g, const double* __restrict__ Q,
-                                                      const double* __restrict__ psi,
-                                                      const double* __restrict__ zeta,
-                                                      double* __restrict__ psiy,
-                                                      double* __restrict__ zetay) {
-    const int k = blockIdx.x * 128 + threadIdx.x;
-    const int j = blockIdx.y;
-    const int f = blockIdx.z;
+__device__ __forceinline__ void spline_dense_body(const Geo& g, const double* __restrict__ Q,
+                                                  const double* __restrict__ psi,
+                                                  const double* __restrict__ zeta,
+                                                  double* __restrict__ psiy,
+                                                  double* __restrict__ zetay, int bx, int j,
+                                                  int f) {
+    const int k = bx * 128 + threadIdx.x;
     if (k >= g.N) return;
     const double* F = (f == 0 ? psi : zeta) + k;
     const double* q = Q + (size_t)j * g.M;
@@ -200,22 +205,29 @@ __global__ __launch_bounds__(128) void k_spline_dense(Geo g, const double* __res
     (f == 0 ? psiy : zetay)[(size_t)j * g.N + k] = t / g.dy;
 }
 
+__global__ __launch_bounds__(128) void k_spline_dense(Geo g, const double* __restrict__ Q,
+                                                      const double* __restrict__ psi,
+                                                      const double* __restrict__ zeta,
+                                                      double* __restrict__ psiy,
+                                                      double* __restrict__ zetay) {
+    spline_dense_body(g, Q, psi, zeta, psiy, zetay, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // Source record (64 B): x, zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
 // FP32 source record (32 B): i (exact), zeta, zeta_x, zeta_y, w psi, w, w zeta_x, -
 // Collocation record (64 B): x*, y*, zeta*, psi*, zeta_x*, zeta_y*, E2 local part, -
 // Eight lanes per grid point: lane 0 writes the source record and, for a collocation
 // point, E1 and the collocation record; the eight log integrals of the closed-form I
 // are spread over the eight lanes and added by shuffles.
-__global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict__ u,
-                                                const double* __restrict__ psi,
-                                                const double* __restrict__ zeta,
-                                                const double* __restrict__ psiy,
-                                                const double* __restrict__ zetay,
-                                                double* __restrict__ src64,
-                                                float* __restrict__ src32,
-                                                double* __restrict__ col,
-                                                double* __restrict__ E) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void points_body(const Geo& g, const double* __restrict__ u,
+                                            const double* __restrict__ psi,
+                                            const double* __restrict__ zeta,
+                                            const double* __restrict__ psiy,
+                                            const double* __restrict__ zetay,
+                                            double* __restrict__ src64, float* __restrict__ src32,
+                                            double* __restrict__ col, double* __restrict__ E,
+                                            int bx) {
+    const int tid = bx * 256 + threadIdx.x;
     const int gi = tid >> 3, sub = tid & 7;
     const bool live = gi < g.NM;  // no early exit: the eight lanes shuffle below
     const int gs = live ? gi : 0;
@@ -271,6 +283,18 @@ __global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict_
     double* r = col + (size_t)c * 8;
     reinterpret_cast<double4*>(r)[0] = make_double4(xs, ys, zs, pss);
     reinterpret_cast<double4*>(r)[1] = make_double4(zxs, zys, base, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_points(Geo g, const double* __restrict__ u,
+                                                const double* __restrict__ psi,
+                                                const double* __restrict__ zeta,
+                                                const double* __restrict__ psiy,
+                                                const double* __restrict__ zetay,
+                                                double* __restrict__ src64,
+                                                float* __restrict__ src32,
+                                                double* __restrict__ col,
+                                                double* __restrict__ E) {
+    points_body(g, u, psi, zeta, psiy, zetay, src64, src32, col, E, blockIdx.x);
 }
 
 // ---- a5: the all-pairs sum ----------------------------------------------------------
@@ -551,10 +575,10 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32_batched(PairBatch b)
 }
 
 // ---- a6: E2 assembly ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict__ col,
-                                                const double* __restrict__ partial, int G,
-                                                double* __restrict__ E) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finish_body(const Geo& g, const double* __restrict__ col,
+                                            const double* __restrict__ partial, int G,
+                                            double* __restrict__ E, int bx) {
+    const int c = bx * 256 + threadIdx.x;
     if (c >= g.ncol) return;
     double t[8] = {};  // eight independent chains: eight loads in flight
     int q = 0;
@@ -566,6 +590,68 @@ __global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict_
     const int l = c / g.Nc;
     const int k = c - l * g.Nc;
     E[(size_t)g.NM + (size_t)l * g.N + k + 1] = col[(size_t)c * 8 + 6] - s;
+}
+
+__global__ __launch_bounds__(256) void k_finish(Geo g, const double* __restrict__ col,
+                                                const double* __restrict__ partial, int G,
+                                                double* __restrict__ E) {
+    finish_body(g, col, partial, G, E, blockIdx.x);
+}
+
+// The prelude and finish of several residuals in one launch each: block b runs block
+// b - first[kind] of the problem it falls in, with the single launch's block shape.
+struct PreProb {
+    Geo g;
+    const double* u;
+    double* E;
+    double* psi;
+    double* zeta;
+    double* psiy;
+    double* zetay;
+    double* src64;
+    float* src32;
+    double* col;
+    const double* Q;  // dense spline operator
+    const double* partial;
+    int G;
+    int first[4];  // first block in the scan, spline, points and finish launches
+};
+constexpr int kMaxPre = 18;  // keeps the kernel argument block under 4 KB
+struct PreBatch {
+    PreProb p[kMaxPre];
+    int nprob;
+};
+static_assert(sizeof(PreBatch) <= 4096, "kernel argument block");
+
+__device__ __forceinline__ int pre_find(const PreBatch& b, int kind, int blk) {
+    int q = 0;
+    while (q + 1 < b.nprob && blk >= b.p[q + 1].first[kind]) ++q;
+    return q;
+}
+
+__global__ __launch_bounds__(64) void k_scan_batched(PreBatch b) {
+    const PreProb& P = b.p[pre_find(b, 0, blockIdx.x)];
+    const int local = blockIdx.x - P.first[0];
+    scan_body(P.g, P.u, P.psi, P.zeta, P.E, local % P.g.M, local / P.g.M);
+}
+
+__global__ __launch_bounds__(128) void k_spline_dense_batched(PreBatch b) {
+    const PreProb& P = b.p[pre_find(b, 1, blockIdx.x)];
+    const int local = blockIdx.x - P.first[1];
+    const int nbx = (P.g.N + 127) / 128;
+    spline_dense_body(P.g, P.Q, P.psi, P.zeta, P.psiy, P.zetay, local % nbx,
+                      (local / nbx) % P.g.M, local / (nbx * P.g.M));
+}
+
+__global__ __launch_bounds__(256) void k_points_batched(PreBatch b) {
+    const PreProb& P = b.p[pre_find(b, 2, blockIdx.x)];
+    points_body(P.g, P.u, P.psi, P.zeta, P.psiy, P.zetay, P.src64, P.src32, P.col, P.E,
+                blockIdx.x - P.first[2]);
+}
+
+__global__ __launch_bounds__(256) void k_finish_batched(PreBatch b) {
+    const PreProb& P = b.p[pre_find(b, 3, blockIdx.x)];
+    finish_body(P.g, P.col, P.partial, P.G, P.E, blockIdx.x - P.first[3]);
 }
 
 // zeta on the grid from the zeta_x half of u: one wavefront per row, the same scan (and
@@ -741,10 +827,41 @@ void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, doub
     Scratch& sc = scratch_for(s, 3);
     sc.ensure(off[nb] + 256);
     std::vector<ResidualBufs> bufs(nb);
+    std::vector<const double*> Q(nb, nullptr);
+    bool batch_pre = true;  // every problem has the dense spline operator
     for (int i = 0; i < nb; ++i) {
         Carve c(static_cast<char*>(sc.base) + off[i]);
         bufs[i] = carve_residual(c, g[i], G[i]);
-        prelude(g[i], u[i], E[i], bufs[i], s);
+        Q[i] = spline_operator(g[i].M, g[i].bc, s);
+        batch_pre = batch_pre && Q[i];
+    }
+    // the preludes of up to kMaxPre problems per launch of each of their three kernels
+    // (a lone residual's launches, run as one), else one problem at a time
+    auto pre_batches = [&](auto&& launch) {
+        for (int i0 = 0; i0 < nb; i0 += kMaxPre) {
+            PreBatch pb{};
+            int tot[4] = {0, 0, 0, 0};
+            for (int i = i0; i < std::min(nb, i0 + kMaxPre); ++i) {
+                PreProb& pp = pb.p[pb.nprob++];
+                pp = PreProb{g[i], u[i], E[i], bufs[i].psi, bufs[i].zeta, bufs[i].psiy,
+                             bufs[i].zetay, bufs[i].src64, bufs[i].src32, bufs[i].col, Q[i],
+                             bufs[i].partial, G[i], {tot[0], tot[1], tot[2], tot[3]}};
+                tot[0] += 2 * g[i].M;
+                tot[1] += ((g[i].N + 127) / 128) * g[i].M * 2;
+                tot[2] += (int)((8 * (size_t)g[i].NM + 255) / 256);
+                tot[3] += (g[i].ncol + 255) / 256;
+            }
+            launch(pb, tot);
+        }
+    };
+    if (batch_pre) {
+        pre_batches([&](const PreBatch& pb, const int* tot) {
+            k_scan_batched<<<tot[0], 64, 0, s>>>(pb);
+            k_spline_dense_batched<<<tot[1], 128, 0, s>>>(pb);
+            k_points_batched<<<tot[2], 256, 0, s>>>(pb);
+        });
+    } else {
+        for (int i = 0; i < nb; ++i) prelude(g[i], u[i], E[i], bufs[i], s);
     }
     const ProfileMark pm = profile_begin(s);
     double pairs = 0.0;
@@ -781,9 +898,15 @@ void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, doub
         flush();
     }
     profile_end(pm, s, pairs);
-    for (int i = 0; i < nb; ++i)
-        k_finish<<<(g[i].ncol + 255) / 256, 256, 0, s>>>(g[i], bufs[i].col, bufs[i].partial,
-                                                        G[i], E[i]);
+    if (batch_pre) {
+        pre_batches([&](const PreBatch& pb, const int* tot) {
+            k_finish_batched<<<tot[3], 256, 0, s>>>(pb);
+        });
+    } else {
+        for (int i = 0; i < nb; ++i)
+            k_finish<<<(g[i].ncol + 255) / 256, 256, 0, s>>>(g[i], bufs[i].col,
+                                                            bufs[i].partial, G[i], E[i]);
+    }
     SW_HIP(hipGetLastError());
 }
 

@@ -1081,25 +1081,31 @@ __global__ __launch_bounds__(256) void k_gemm(int n, double alpha, GemmBatch bat
             }
 }
 
-// The Schur update of one eliminated block row l as a single product: with nbr the nn
-// rows coupled to l, C(a, b) += alpha A_a G_b for a, b < nn, where A_a = S(nbr[a], l),
-// G_b the b-th block of G and C(a, b) = S(nbr[a], nbr[b]).  The (nn N) x (nn N) x N
-// product is tiled as one matrix whose rows run over (a, i) and columns over (b, j), so
-// only its last tile row and column are padded, where a 721^3 block product alone pads
-// 721 to 768 in both dimensions (13% of its matrix-core work).  A pair that is not in
-// the mask is neither updated nor, where a whole tile lies in such pairs, computed.
+// Products of one eliminated block row l, each as a single product whose rows run over
+// (a, i) and columns over (b, j): C(a, b) = [C(a, b) +] alpha A_a B_b for a < na, b < nb.
+//   Schur update: A_a = S(nbr[a], l), B_b = G_{l, nbr[b]}, C(a, b) = S(nbr[a], nbr[b]),
+//                 accumulated, alpha = -1 (na = nb = number of coupled rows);
+//   L = S(nbr[a], l) Dinv_l: nb = 1, B_0 = Dinv_l;   G = Dinv_l S(l, nbr[b]): na = 1.
+// As one (na N) x (nb N) x N product only its last tile row and column are padded, where
+// a 721^3 block product alone pads 721 to 768 in both dimensions (13% of its
+// matrix-core work).  A pair that is not in the mask is neither updated nor, where a
+// whole tile lies in such pairs, computed.
 constexpr int kMaxRowNbr = 32;
 struct RowProd {
     const double* A[kMaxRowNbr];  // A_a, N x N row-major
     double* Crow[kMaxRowNbr];     // C(a, b) = Crow[a] + b N^2
-    const double* G;              // G_b = G + b N^2
-    unsigned mask[kMaxRowNbr];    // bit b of word a: pair (a, b) is updated
-    int nn;
+    const double* B;              // B_b = B + b N^2
+    unsigned mask[kMaxRowNbr];    // bit b of word a: pair (a, b) is computed
+    int na, nb;
+    int accumulate;               // C += alpha A B, else C = alpha A B
 };
+constexpr int kMaxRowProds = 4;
 struct RowProdArgs {
-    RowProd p[2];
-    int tiles0;  // tiles of problem 0; the rest of the grid is problem 1
+    RowProd p[kMaxRowProds];
+    int first[kMaxRowProds];  // first tile of each problem in the grid
+    int np;
 };
+static_assert(sizeof(RowProdArgs) <= 4096, "kernel argument block");
 
 // 64 x 64 tile per 256-thread workgroup, 2 x 2 wavefronts of 2 x 2 v_mfma_f64_16x16x4f64
 // tiles, K in slices of 16 double-buffered in LDS through a register prefetch (one
@@ -1109,21 +1115,22 @@ struct RowProdArgs {
 // eight tile rows at a time, column by column, and consecutive tiles stay on one XCD.
 // Each element's K sum runs in the same order as in k_gemm, so the two give the same
 // bits.
-__global__ __launch_bounds__(256) void k_schur_rows(int N, double alpha, RowProdArgs args) {
+__global__ __launch_bounds__(256) void k_row_products(int N, double alpha, RowProdArgs args) {
     constexpr int T = 64, KS = 16, RA = 4, RB = 4, AR = 16, BKP = 4, kGroup = 8;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int pi = lin < args.tiles0 ? 0 : 1;
+    int pi = 0;
+    while (pi + 1 < args.np && lin >= args.first[pi + 1]) ++pi;
     const RowProd& P = args.p[pi];
-    const int tile = lin - (pi ? args.tiles0 : 0);
-    const int nt = P.nn * N;
-    const int tpd = (nt + T - 1) / T;
-    const int grp = tile / (kGroup * tpd);
-    const int gsz = min(kGroup, tpd - grp * kGroup);
-    const int within = tile - grp * kGroup * tpd;
+    const int tile = lin - args.first[pi];
+    const int ntr = P.na * N, ntc = P.nb * N;
+    const int tpm = (ntr + T - 1) / T, tpn = (ntc + T - 1) / T;
+    const int grp = tile / (kGroup * tpn);
+    const int gsz = min(kGroup, tpm - grp * kGroup);
+    const int within = tile - grp * kGroup * tpn;
     const int row0 = (grp * kGroup + within % gsz) * T, col0 = (within / gsz) * T;
     {
-        const int a0 = row0 / N, a1 = (min(row0 + T, nt) - 1) / N;
-        const int b0 = col0 / N, b1 = (min(col0 + T, nt) - 1) / N;
+        const int a0 = row0 / N, a1 = (min(row0 + T, ntr) - 1) / N;
+        const int b0 = col0 / N, b1 = (min(col0 + T, ntc) - 1) / N;
         unsigned any = 0;
         for (int a = a0; a <= a1; ++a) any |= P.mask[a] >> b0 & ((2u << (b1 - b0)) - 1u);
         if (!any) return;
@@ -1143,16 +1150,16 @@ __global__ __launch_bounds__(256) void k_schur_rows(int N, double alpha, RowProd
     const double* arow[RA];
 #pragma unroll
     for (int e = 0; e < RA; ++e) {
-        const int r = min(row0 + ar + AR * e, nt - 1);
+        const int r = min(row0 + ar + AR * e, ntr - 1);
         const int a = r / N;
         arow[e] = P.A[a] + (size_t)(r - a * N) * N;
     }
     const int bcl = t % T, bk0 = t / T;
     const double* bcolp;
     {
-        const int c = min(col0 + bcl, nt - 1);
+        const int c = min(col0 + bcl, ntc - 1);
         const int b = c / N;
-        bcolp = P.G + (size_t)b * N * N + (c - b * N);
+        bcolp = P.B + (size_t)b * N * N + (c - b * N);
     }
     double ra[RA], rb[RB];
     unsigned bmask[RB];
@@ -1213,9 +1220,9 @@ __global__ __launch_bounds__(256) void k_schur_rows(int N, double alpha, RowProd
             for (int r = 0; r < 4; ++r) {
                 const int rr = row0 + wr + a * 16 + (lane >> 4) + 4 * r;
                 const int aa = rr / N, i = rr - aa * N;
-                if (rr < nt && c < nt && ((P.mask[aa] >> bb) & 1u)) {
+                if (rr < ntr && c < ntc && ((P.mask[aa] >> bb) & 1u)) {
                     double* o = P.Crow[aa] + (size_t)bb * N * N + (size_t)i * N + j;
-                    *o = *o + alpha * acc[a][b][r];
+                    *o = (P.accumulate ? *o : 0.0) + alpha * acc[a][b][r];
                 }
             }
     }
@@ -1622,22 +1629,25 @@ void gemm_batched(int n, double alpha, const std::vector<GemmJob>& jobs, hipStre
     }
 }
 
-// Row products (k_schur_rows) of up to two eliminated rows in one launch; problems whose
-// mask is empty are dropped.
-void schur_rows(int N, double alpha, const RowProd* rp, int np, hipStream_t s) {
+// Row products (k_row_products), up to four per launch; problems whose mask is empty are
+// dropped.
+void row_products(int N, double alpha, const RowProd* rp, int np, hipStream_t s) {
     RowProdArgs args{};
-    int tiles[2] = {0, 0}, k = 0;
+    int total = 0;
     for (int i = 0; i < np; ++i) {
         unsigned any = 0;
-        for (int a = 0; a < rp[i].nn; ++a) any |= rp[i].mask[a];
+        for (int a = 0; a < rp[i].na; ++a) any |= rp[i].mask[a];
         if (!any) continue;
-        args.p[k] = rp[i];
-        const int tpd = (rp[i].nn * N + 63) / 64;
-        tiles[k++] = tpd * tpd;
+        if (args.np == kMaxRowProds) {
+            k_row_products<<<total, 256, 0, s>>>(N, alpha, args);
+            args = RowProdArgs{};
+            total = 0;
+        }
+        args.p[args.np] = rp[i];
+        args.first[args.np++] = total;
+        total += ((rp[i].na * N + 63) / 64) * ((rp[i].nb * N + 63) / 64);
     }
-    if (k == 0) return;
-    args.tiles0 = tiles[0];
-    k_schur_rows<<<tiles[0] + tiles[1], 256, 0, s>>>(N, alpha, args);
+    if (args.np > 0) k_row_products<<<total, 256, 0, s>>>(N, alpha, args);
 }
 
 
@@ -1865,11 +1875,11 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
         std::vector<GemmJob> jobs1 = pendingL, diag_a, diag_b, rest_a, rest_b;
         pendingL.clear();
         std::vector<const double*> top_targets;
-        // with N > 256 and consecutive coupled rows, a row's Schur updates outside the
-        // diagonal launches run as one row product (rp_rest, and rp_late for the bottom
-        // updates that must wait for the top chain's)
-        RowProd rp_rest[2], rp_late[2];
-        int nrp = 0;
+        // with N > 256 and consecutive coupled rows, a row's L and G run as two row
+        // products (rp_lg) and its Schur updates outside the diagonal launches as one
+        // (rp_rest, and rp_late for the bottom updates that must wait for the top chain's)
+        RowProd rp_lg[4], rp_rest[2], rp_late[2];
+        int nrp = 0, nlg = 0;
         for (int e = 0; e < nr; ++e) {
             const int l = rows[e];
             const int ch = (step < ns && l >= o.k) ? 1 : 0;
@@ -1880,31 +1890,57 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
             if (nbr.empty()) continue;
             double* sc = half(ch, step & 1);
             const int nn = (int)nbr.size();
-            for (int a = 0; a < nn; ++a)
-                jobs1.push_back(GemmJob{Sb(nbr[a], l), Sb(l, l), nullptr, sc + (size_t)a * NN});
-            for (int b = 0; b < nn; ++b)
-                jobs1.push_back(
-                    GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
-            // the product addresses C(a, b) as C(a, 0) + b N^2: the coupled rows must be
-            // consecutive band rows
+            // the products address C(a, b) as C(a, 0) + b N^2 and G's right factors
+            // S(l, nbr[b]) as S(l, nbr[0]) + b N^2: the coupled rows must be consecutive
+            // band rows
             bool consecutive = g.N > 256 && nn <= kMaxRowNbr;
             for (int a = 0; a < nn && consecutive; ++a)
                 for (int b = 0; b < nn && consecutive; ++b)
-                    consecutive = Sb(nbr[a], nbr[b]) == Sb(nbr[a], nbr[0]) + (size_t)b * NN;
+                    consecutive = Sb(nbr[a], nbr[b]) == Sb(nbr[a], nbr[0]) + (size_t)b * NN &&
+                                  Sb(l, nbr[b]) == Sb(l, nbr[0]) + (size_t)b * NN;
             RowProd* rr = nullptr;
             RowProd* rl = nullptr;
             if (consecutive) {
+                const unsigned all = (nn == 32) ? ~0u : ((1u << nn) - 1u);
+                // L_{nbr[a], l} = S(nbr[a], l) Dinv_l into the scratch's first nn blocks
+                RowProd& L = rp_lg[nlg++];
+                L = RowProd{};
+                L.B = Sb(l, l);
+                L.na = nn;
+                L.nb = 1;
+                for (int a = 0; a < nn; ++a) {
+                    L.A[a] = Sb(nbr[a], l);
+                    L.Crow[a] = sc + (size_t)a * NN;
+                    L.mask[a] = 1u;
+                }
+                // G_{l, nbr[b]} = Dinv_l S(l, nbr[b]) into blocks q, q + 1, ...
+                RowProd& Gp = rp_lg[nlg++];
+                Gp = RowProd{};
+                Gp.A[0] = Sb(l, l);
+                Gp.B = Sb(l, nbr[0]);
+                Gp.Crow[0] = sc + (size_t)q * NN;
+                Gp.mask[0] = all;
+                Gp.na = 1;
+                Gp.nb = nn;
                 rr = &rp_rest[nrp];
                 rl = &rp_late[nrp];
                 ++nrp;
                 *rr = RowProd{};
-                rr->G = sc + (size_t)q * NN;
-                rr->nn = nn;
+                rr->B = sc + (size_t)q * NN;
+                rr->na = rr->nb = nn;
+                rr->accumulate = 1;
                 for (int a = 0; a < nn; ++a) {
                     rr->A[a] = Sb(nbr[a], l);
                     rr->Crow[a] = Sb(nbr[a], nbr[0]);
                 }
                 *rl = *rr;
+            } else {
+                for (int a = 0; a < nn; ++a)
+                    jobs1.push_back(
+                        GemmJob{Sb(nbr[a], l), Sb(l, l), nullptr, sc + (size_t)a * NN});
+                for (int b = 0; b < nn; ++b)
+                    jobs1.push_back(
+                        GemmJob{Sb(l, l), Sb(l, nbr[b]), nullptr, sc + (size_t)(q + b) * NN});
             }
             for (int a = 0; a < nn; ++a)
                 for (int b = 0; b < nn; ++b) {
@@ -1929,6 +1965,7 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
                 pendingL.push_back(GemmJob{sc + (size_t)a * NN, nullptr, nullptr, Sb(nbr[a], l)});
         }
         if (!jobs1.empty()) gemm_batched(g.N, 1.0, jobs1, s);
+        row_products(g.N, 1.0, rp_lg, nlg, s);
         hipStream_t rs = s;
         if (s2 && (!rest_a.empty() || !rest_b.empty() || nrp > 0)) {
             hipEvent_t e = new_event();
@@ -1938,9 +1975,9 @@ void factor_band(sw_precond* P, const Order& o, hipStream_t s, hipStream_t s2,
         }
         if (!diag_a.empty()) gemm_batched(g.N, -1.0, diag_a, s);
         if (!diag_b.empty()) gemm_batched(g.N, -1.0, diag_b, s);
-        schur_rows(g.N, -1.0, rp_rest, nrp, rs);
+        row_products(g.N, -1.0, rp_rest, nrp, rs);
         if (!rest_a.empty()) gemm_batched(g.N, -1.0, rest_a, rs);
-        schur_rows(g.N, -1.0, rp_late, nrp, rs);
+        row_products(g.N, -1.0, rp_late, nrp, rs);
         if (!rest_b.empty()) gemm_batched(g.N, -1.0, rest_b, rs);
         if (rs != s) {
             side_done = new_event();

@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="serving workload: Poisson arrivals of mixed solves (prints its own line)")
     ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--out-dir", default=None,
+                    help="folder for the detail files of --serving, --table1 and "
+                         "--precond-study (per-request times, centrelines, spectra); "
+                         "none are written without it")
     ap.add_argument("--serving-rate", type=float, default=None,
                     help="Poisson arrival rate of --serving (default: 80%% of the closed-loop "
                          "mixed capacity)")
@@ -254,9 +258,9 @@ def main():
     if args.workloads:
         return workloads()
     if args.table1:
-        return table1()
+        return table1(args.out_dir)
     if args.precond_study:
-        return precond_study()
+        return precond_study(args.out_dir)
     import torch
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
@@ -417,7 +421,7 @@ def extra_measurements(api, inputs, cfg, one_solve, z64, args):
                    "solve's own max|E32 - E64| / max(1, ||E64||) over every entry")
     res["fp32_error"] = err
     print(f"mixed solve: {res['mixed_solve']}; fp32 error {err}", file=sys.stderr, flush=True)
-    res["serving"] = serving_runs(api, inputs, args.requests)
+    res["serving"] = serving_runs(api, inputs, args.requests, out_dir=args.out_dir)
     return res
 
 
@@ -434,7 +438,7 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "dispatches": 3}))
 
 
-def serving_runs(api, inputs, nreq, fixed_rate=None):
+def serving_runs(api, inputs, nreq, fixed_rate=None, out_dir=None):
     """Serving workload: requests with Poisson arrivals, meshes uniform over
     {61x21, 121x41, 181x61, 241x81} on x in [-16, 8], y in [0, 12],
     F ~ U[0.5, 1.0], eps ~ U[0.05, 0.4] (seed 0).  First a closed-loop run
@@ -445,7 +449,7 @@ def serving_runs(api, inputs, nreq, fixed_rate=None):
     import numpy as np
     dom = inputs.SERVING_DOMAIN
 
-    dump = [] if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    dump = [] if out_dir else None
 
     def run(srv, reqs, rate=None):
         t0 = time.perf_counter()
@@ -495,7 +499,8 @@ def serving_runs(api, inputs, nreq, fixed_rate=None):
         print(f"serving poisson {prec}: {out[f'poisson_{prec}']}", file=sys.stderr, flush=True)
     out["arrival_rate_per_s"] = rate
     if dump is not None:
-        with open(os.path.join(ROOT, "gpurun_out", "serving_requests.json"), "w") as f:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "serving_requests.json"), "w") as f:
             json.dump(dump, f)
     how = "fixed" if fixed_rate else "80% of closed-loop mixed capacity"
     out["workload"] = (f"serving: {nreq} requests, Poisson arrivals at {rate:.2f}/s ({how}), "
@@ -509,7 +514,7 @@ def serving(args):
     from paper_1403_5044_amd import api, inputs
     from paper_1403_5044_amd import _lib
     _lib.load()
-    out = serving_runs(api, inputs, args.requests, args.serving_rate)
+    out = serving_runs(api, inputs, args.requests, args.serving_rate, args.out_dir)
     line = {"metric": METRIC,
             "value": out["poisson_fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
             "steps": args.requests, "warmup": args.requests, "higher_is_better": True,
@@ -665,12 +670,12 @@ def _continue(api, cfg, F, eps_list, prec, q, kw, log):
     return u, z, {"build_s": build_s, "q": q, "precision": prec, "steps": steps}
 
 
-def table1():
+def table1(out_dir=None):
     """The paper's headline workload, eps = 1 and F = 0.7 (results section):
     function-evaluation times on the Table-1 meshes beside Table 1; roots at eps = 1
     on 91 x 31, 361 x 121 and 721 x 241 by eps continuation in steps of 0.1 from the
     flat surface; their centrelines zeta(x, 0); and F = 1.4 on 721 x 241 with spacing
-    0.3 from x_1 = -56.  Writes the centrelines to gpurun_out/table1_centrelines.json
+    0.3 from x_1 = -56.  Writes the centrelines to table1_centrelines.json in out_dir
     when that folder exists."""
     import numpy as np
     import torch
@@ -746,8 +751,9 @@ def table1():
         cmp[f"{name}_zeta_max_at_x"] = [float(zc.max()), float(xc[zc.argmax()])]
         cmp[f"{name}_zeta_min_at_x"] = [float(zc.min()), float(xc[zc.argmin()])]
     out["centreline_comparison"] = cmp
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", "table1_centrelines.json"), "w") as f:
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "table1_centrelines.json"), "w") as f:
             json.dump(out["centreline"], f)
     del out["centreline"]
     ev = out["evaluations"]
@@ -758,7 +764,7 @@ def table1():
           flush=True)
 
 
-def precond_study():
+def precond_study(out_dir=None):
     """The preconditioner study (preconditioning section): GMRES iterations per
     Newton step against the block bandwidth b = 2q + 1 at 361 x 121 (eps = 1, F = 0.7,
     from the eps = 0.9 root) and for cold solves of the benched 721 x 241 workload, and
@@ -846,8 +852,9 @@ def precond_study():
         out["spectra"][key] = _spectrum_summary(evp)
         spectra[key] = [evp.real.tolist(), evp.imag.tolist()]
         log(f"{key}: {out['spectra'][key]}")
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", "precond_spectra.json"), "w") as f:
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "precond_spectra.json"), "w") as f:
             json.dump(spectra, f)
     best = min(out["bandwidth_sweep"], key=lambda r: r["build_s"] + r["solve_s"])
     print(json.dumps(_line(best["gmres_per_newton"], "GMRES iterations per Newton step",

@@ -233,6 +233,66 @@ class BlockPreconditioner:
         return P
 
 
+def K3_row(prob: Problem, l: int, m: int, k: int) -> np.ndarray:
+    """Row k of K3_block(prob, l, m): K3(x_n, y_m; x*_k, y*_l) for n = 0..N-1."""
+    n = np.arange(prob.N)
+    dx = (n - k - 0.5) * prob.dx
+    dy = (m - l) * prob.dy
+    dyp = (m + l) * prob.dy
+    return 1.0 / np.sqrt(dx * dx + dy * dy) + 1.0 / np.sqrt(dx * dx + dyp * dyp)
+
+
+def K3_sum_at(prob: Problem, l: int, k: int) -> float:
+    """sum_{i,j} w(i,j) K3(i,j;k,l) at one collocation point (K3_sums(prob)[l, k])."""
+    w = weights(prob)
+    return float(sum(K3_row(prob, l, m, k) @ w[m] for m in range(prob.M)))
+
+
+def p_rows(prob: Problem, q: int, rows, x: np.ndarray, absolute: bool = False) -> np.ndarray:
+    """Entries `rows` of P x for the preconditioner matrix P = [[A, B], [C, D_q]]
+    (BlockPreconditioner.matrix()), formed row by row from the blocks, so that meshes
+    too large for a dense P can be checked on sampled rows.  With absolute = True the
+    entries of |P| |x| instead."""
+    N, M = prob.N, prob.M
+    NM = N * M
+    f = np.abs if absolute else (lambda a: a)
+    x1 = f(x[:NM]).reshape(M, N)
+    x2 = f(x[NM:]).reshape(M, N)
+    A = f(A_block(prob))
+    T = T_block(prob)
+    B = f(T / prob.F ** 2)
+    C = f(TWO_PI * T)
+    w = weights(prob)
+    Il = None
+    out = np.empty(len(rows))
+    for t, r in enumerate(rows):
+        r = int(r)
+        if r < NM:
+            l, k = divmod(r, N)
+            out[t] = A[k] @ x1[l] + B[k] @ x2[l]
+            continue
+        l, c = divmod(r - NM, N)
+        v = C[c] @ x1[l]
+        for m in range(max(0, l - q), min(M - 1, l + q) + 1):
+            # row c of D_block(prob, l, m)
+            d = np.zeros(N)
+            if c == 0:
+                if m == l:
+                    d[0] = prob.nu - prob.x1 / prob.dx
+                    d[1] = prob.x1 / prob.dx
+            else:
+                d[:] = -K3_row(prob, l, m, c - 1) * w[m]
+                if m == l:
+                    if Il is None:
+                        Il = I_lin(prob)
+                    half = 0.5 * (K3_sum_at(prob, l, c - 1) - Il[l, c - 1])
+                    d[c - 1] += half
+                    d[c] += half
+            v += f(d) @ x2[m]
+        out[t] = v
+    return out
+
+
 def linear_solution(prob: Problem, pre: BlockPreconditioner | None = None) -> np.ndarray:
     """Root of the discrete linear system: u_flat - eps J_lin^{-1} s (dense Schur solve)."""
     from .problem import flat_state

@@ -360,3 +360,25 @@ def test_full_linear_preconditioner_solves_linear_problem_in_one_iteration():
     np.testing.assert_allclose(pre.solve(J @ v), v, rtol=0, atol=1e-9 * np.abs(v).max())
     x, its, res = gmres(lambda y: J @ y, b, pre.solve, tol=1e-10 * np.linalg.norm(b))
     assert its == 1
+
+
+@pytest.mark.parametrize("q", [0, 2, 6])
+@pytest.mark.parametrize("rule", ["trapezoid", "simpson"])
+def test_row_wise_p_times_x_equals_the_dense_preconditioner(q, rule):
+    """p_rows forms entries of P x from the blocks without a dense P (for meshes whose P
+    does not fit); on every row of a small mesh it must equal BlockPreconditioner's
+    dense matrix times x, and with absolute=True |P| |x|.  K3_sum_at must equal the
+    sums that the dense D uses."""
+    prob = C1.with_(weights=rule)
+    Pm = L.BlockPreconditioner(prob, q).matrix()
+    x = np.random.default_rng(q).standard_normal(prob.n_unknowns)
+    rows = np.arange(prob.n_unknowns)
+    y = L.p_rows(prob, q, rows, x)
+    ya = L.p_rows(prob, q, rows, x, absolute=True)
+    scale = np.abs(Pm) @ np.abs(x)
+    assert np.abs(y - Pm @ x).max() <= 1e-14 * scale.max()
+    assert np.abs(ya - scale).max() <= 1e-14 * scale.max()
+    S = L.K3_sums(prob)
+    for l in (0, 3, prob.M - 1):
+        for k in (0, 7, prob.N - 2):
+            assert abs(L.K3_sum_at(prob, l, k) - S[l, k]) <= 1e-14 * abs(S[l, k])

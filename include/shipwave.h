@@ -91,9 +91,10 @@ typedef struct {
 } sw_params;
 typedef struct { sw_mesh mesh; sw_domain domain; sw_params params; } sw_problem;
 
-/* Validation shared by all calls: N, M >= 4; N <= 1024; F > 0; eps >= 0;
- * nu > 0; x_1 < 0 < x_N is not required, but x_1 < x_N, y_M > 0; Simpson needs
- * odd N and M.  Violations return SW_EINVAL. */
+/* Validation shared by all calls: N, M >= 4; N <= 65536 and N M <= 2^28; F > 0;
+ * eps >= 0; nu > 0; x_1 < 0 < x_N is not required, but x_1 < x_N, y_M > 0; Simpson
+ * needs odd N and M.  Calls that build or use a preconditioner (precond_build_banded,
+ * solve, server requests) also need N <= 1024.  Violations return SW_EINVAL. */
 
 int32_t shipwave_abi_version(void);
 const char* shipwave_last_error(void);

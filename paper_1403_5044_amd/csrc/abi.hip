@@ -17,7 +17,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 Geo make_geo(const sw_problem& p) {
     const int N = p.mesh.N, M = p.mesh.M;
     SW_REQUIRE(N >= 4 && M >= 4, "N and M must be >= 4");
-    SW_REQUIRE(N <= kMaxN, "N must be <= 1024");
+    SW_REQUIRE(N <= kMaxGridN, "N must be <= 65536");
     SW_REQUIRE((long long)N * M <= (1LL << 28), "mesh too large");
     const sw_domain& d = p.domain;
     SW_REQUIRE(std::isfinite(d.x1) && std::isfinite(d.xN) && d.x1 < d.xN, "need x1 < xN");

@@ -2218,6 +2218,7 @@ void precond_release(void* p, size_t bytes, int dev) {
 }  // namespace
 
 sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
+    SW_REQUIRE(g0.N <= kMaxN, "the preconditioner needs N <= 1024");
     Geo g = g0;
     g.precision = SW_PREC_FP64;
     const int q = std::max(0, std::min(q_req, g.M - 1));

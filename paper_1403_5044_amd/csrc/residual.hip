@@ -308,6 +308,8 @@ __device__ __forceinline__ double rsq2_64(double x) {
 }
 
 constexpr int kPairThreads = 256;
+// source records staged in LDS at a time (64 KB of FP64 records, 32 KB of FP32 ones)
+constexpr int kPairSeg = 1024;
 #ifndef SW_UNROLL64
 #define SW_UNROLL64 2  // source points per FP64 inner-loop iteration
 #endif
@@ -350,13 +352,6 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
     }
     for (int j = s0 / N; j * N < s1; ++j) {
         const int i0 = max(0, s0 - j * N), i1 = min(N, s1 - j * N);
-        __syncthreads();
-        {
-            const double2* srow = reinterpret_cast<const double2*>(src + (size_t)j * N * 8);
-            double2* dst = reinterpret_cast<double2*>(lds);
-            for (int t = i0 * 4 + tid; t < i1 * 4; t += kPairThreads) dst[t] = srow[t];
-        }
-        __syncthreads();
         double dy[CP], dyp[CP], dy2[CP], ddy[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
 #pragma unroll
         for (int c = 0; c < CP; ++c) {
@@ -370,10 +365,22 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
             Cdy2[c] = C[c] * dy2[c];
             Cdyp2[c] = C[c] * (dyp[c] * dyp[c]);
         }
+        // the row's sources in segments of at most kPairSeg records (one segment for
+        // N <= kPairSeg)
+        for (int a = i0; a < i1; a += kPairSeg) {
+        const int b = min(i1, a + kPairSeg);
+        __syncthreads();
+        {
+            const double2* srow =
+                reinterpret_cast<const double2*>(src + ((size_t)j * N + a) * 8);
+            double2* dst = reinterpret_cast<double2*>(lds);
+            for (int t = tid; t < (b - a) * 4; t += kPairThreads) dst[t] = srow[t];
+        }
+        __syncthreads();
 #pragma unroll SW_UNROLL64
-        for (int i = i0; i < i1; ++i) {
-            const double4 r0 = reinterpret_cast<const double4*>(lds + i * 8)[0];
-            const double4 r1 = reinterpret_cast<const double4*>(lds + i * 8)[1];
+        for (int i = a; i < b; ++i) {
+            const double4 r0 = reinterpret_cast<const double4*>(lds + (i - a) * 8)[0];
+            const double4 r1 = reinterpret_cast<const double4*>(lds + (i - a) * 8)[1];
             const double sx = r0.x, sz = r0.y, szx = r0.z, szy = r0.w;
             const double swp = r1.x, sw = r1.y, swzx = r1.z;
 #pragma unroll
@@ -401,6 +408,7 @@ __device__ __forceinline__ void pairs_f64_body(const Geo& g, const double* __res
                 acc2[c] = fma(swzx, i1 + i2, acc2[c]);
                 acc3[c] = fma(sw, js, acc3[c]);
             }
+        }
         }
     }
 #pragma unroll
@@ -463,13 +471,6 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
     }
     for (int j = lo / N; j * N < hi; ++j) {
         const int i0 = max(0, lo - j * N), i1 = min(N, hi - j * N);
-        __syncthreads();
-        {
-            const float4* srow = reinterpret_cast<const float4*>(src + (size_t)j * N * 8);
-            float4* dst = reinterpret_cast<float4*>(lds);
-            for (int t = i0 * 2 + tid; t < i1 * 2; t += kPairThreads) dst[t] = srow[t];
-        }
-        __syncthreads();
         float dy[CP], dyp[CP], dy2[CP], ddy[CP], Bdy[CP], mBdyp[CP], Cdy2[CP], Cdyp2[CP];
         float r1[CP], r2[CP], r3[CP];
 #pragma unroll
@@ -484,10 +485,19 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
             Cdyp2[c] = C[c] * (dyp[c] * dyp[c]);
             r1[c] = r2[c] = r3[c] = 0.0f;
         }
+        for (int a = i0; a < i1; a += kPairSeg) {
+        const int b = min(i1, a + kPairSeg);
+        __syncthreads();
+        {
+            const float4* srow = reinterpret_cast<const float4*>(src + ((size_t)j * N + a) * 8);
+            float4* dst = reinterpret_cast<float4*>(lds);
+            for (int t = tid; t < (b - a) * 2; t += kPairThreads) dst[t] = srow[t];
+        }
+        __syncthreads();
 #pragma unroll 2
-        for (int i = i0; i < i1; ++i) {
-            const float4 s0 = reinterpret_cast<const float4*>(lds + i * 8)[0];
-            const float4 s1 = reinterpret_cast<const float4*>(lds + i * 8)[1];
+        for (int i = a; i < b; ++i) {
+            const float4 s0 = reinterpret_cast<const float4*>(lds + (i - a) * 8)[0];
+            const float4 s1 = reinterpret_cast<const float4*>(lds + (i - a) * 8)[1];
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
                 const float dx = (s0.x + t0[c]) * fdx;
@@ -508,6 +518,7 @@ __device__ __forceinline__ void pairs_f32_body(const Geo& g, const float* __rest
                 r2[c] = fmaf(s1.z, i1 + i2, r2[c]);
                 r3[c] = fmaf(s1.y, j1s + j2s, r3[c]);
             }
+        }
         }
 #pragma unroll
         for (int c = 0; c < CP; ++c) kahan_add(S[c], comp[c], (r1[c] + r2[c]) - zxs[c] * r3[c]);
@@ -767,11 +778,11 @@ void residual_enqueue(const Geo& g, const double* u, double* E, const ResidualBu
     const ProfileMark pm = profile_begin(s);
     if (g.precision == SW_PREC_FP32) {
         const int ntiles = (g.ncol + kPairThreads * kCP32 - 1) / (kPairThreads * kCP32);
-        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)g.N * 32, s>>>(
+        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)std::min(g.N, kPairSeg) * 32, s>>>(
             g, b.src32, b.col, b.partial, ntiles, b.G);
     } else {
         const int ntiles = (g.ncol + kPairThreads * kCP64 - 1) / (kPairThreads * kCP64);
-        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)g.N * 64, s>>>(
+        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)std::min(g.N, kPairSeg) * 64, s>>>(
             g, b.src64, b.col, b.partial, ntiles, b.G);
     }
     profile_end(pm, s, (double)g.ncol * (double)g.NM);
@@ -787,11 +798,11 @@ void residual_enqueue_fixed(const Geo& g, const double* u, double* E, const Resi
     prelude(g, u, E, b, s, false);
     if (g.precision == SW_PREC_FP32) {
         const int ntiles = (g.ncol + kPairThreads * kCP32 - 1) / (kPairThreads * kCP32);
-        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)g.N * 32, s>>>(
+        k_pairs_f32<kCP32><<<ntiles * b.G, kPairThreads, (size_t)std::min(g.N, kPairSeg) * 32, s>>>(
             g, b.src32, b.col, b.partial, ntiles, b.G);
     } else {
         const int ntiles = (g.ncol + kPairThreads * kCP64 - 1) / (kPairThreads * kCP64);
-        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)g.N * 64, s>>>(
+        k_pairs_f64<kCP64><<<ntiles * b.G, kPairThreads, (size_t)std::min(g.N, kPairSeg) * 64, s>>>(
             g, b.src64, b.col, b.partial, ntiles, b.G);
     }
     k_finish<<<(g.ncol + 255) / 256, 256, 0, s>>>(g, b.col, b.partial, b.G, E);
@@ -871,7 +882,7 @@ void residual_batched_enqueue(int nb, const Geo* g, const double* const* u, doub
         int maxN = 0;
         auto flush = [&]() {
             if (batch.nprob == 0) return;
-            const size_t lds = (size_t)maxN * (prec == SW_PREC_FP32 ? 32 : 64);
+            const size_t lds = (size_t)std::min(maxN, kPairSeg) * (prec == SW_PREC_FP32 ? 32 : 64);
             if (prec == SW_PREC_FP32)
                 k_pairs_f32_batched<kCP32><<<batch.total, kPairThreads, lds, s>>>(batch);
             else

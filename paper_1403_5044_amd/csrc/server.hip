@@ -162,7 +162,9 @@ Geo request_geo(const sw_request& req) {
     p.params.eps = req.eps;
     p.params.nu = 0.05;
     p.params.precision = SW_PREC_FP64;
-    return make_geo(p);
+    const Geo g = make_geo(p);
+    SW_REQUIRE(g.N <= kMaxN, "a request needs a preconditioner, which needs N <= 1024");
+    return g;
 }
 
 // device bytes of one admitted request, besides its preconditioner: its solve state, its

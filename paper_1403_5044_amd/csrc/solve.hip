@@ -410,6 +410,7 @@ int32_t solve_impl(double F, double eps, const sw_mesh* mesh, const sw_domain* d
     p.params.spline_bc = o.spline_bc;
     p.params.precision = o.precision;
     const Geo g = make_geo(p);  // validates the inner precision too
+    SW_REQUIRE(g.N <= kMaxN, "a solve needs a preconditioner, which needs N <= 1024");
     SolveParams prm;
     prm.tol = o.tol;
     prm.max_newton = o.max_newton;

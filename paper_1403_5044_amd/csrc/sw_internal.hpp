@@ -60,7 +60,12 @@ struct Geo {
     double F, eps, nu;
 };
 
-constexpr int kMaxN = 1024;  // one source row (N x 64 B) must fit in 64 KB of LDS
+// Mesh widths: the residual, JVP and zeta calls stage source rows through LDS in
+// segments, so any N up to kMaxGridN works there; the preconditioner's apply kernels
+// hold a block row in LDS and its wide-block inversion at most four panel rows per
+// thread, so preconditioners (and hence solves and server requests) need N <= kMaxN.
+constexpr int kMaxN = 1024;
+constexpr int kMaxGridN = 1 << 16;
 
 Geo make_geo(const sw_problem& p);  // validates, throws SW_EINVAL
 

@@ -76,3 +76,6 @@ def test_request_footprint_query_is_host_only_and_monotone():
     assert charge(181, 61, 4)[1] > small
     assert charge(181, 61, 8)[1] > charge(181, 61, 4)[1]
     assert charge(3, 21, 4)[0] == -1
+    # a request needs a preconditioner, and a preconditioner N <= 1024
+    assert charge(1024, 5, 2)[0] == 0
+    assert charge(1025, 5, 2)[0] == -1

@@ -105,6 +105,41 @@ def test_fp32_kahan_residual_error_is_small(name, cfg):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("N", [1025, 2050])
+def test_residual_parity_beyond_one_lds_segment(N):
+    """Meshes wider than the 1024 source records that one LDS stage holds: the pair
+    kernels take a row in segments (1025 = 1024 + 1, 2050 = 1024 + 1024 + 2).  FP64
+    against the oracle at the usual gate, FP32-Kahan within 2^-19 of the row scale
+    (the bound of the FP32 reading), and the batched residual bitwise equal to the
+    single one."""
+    cfg = dict(N=N, M=5, x1=-20.0, xN=20.0, yM=2.0, F=0.7, eps=0.2)
+    p = gprob(cfg)
+    u = inputs.smooth_state(p.N, p.M, 0.05, 6)
+    E = gpu_residual(p, u)
+    _check(f"wide{N}x5", p, u, E)
+    op = oprob(p)
+    E32 = gpu_residual(p.with_(precision="fp32"), u)
+    err32 = (np.abs(E32 - oresidual(op, u)) / row_scale(op, u)).max()
+    log(f"wide{N}x5: FP32-Kahan max rel err vs FP64 oracle {err32:.3e}")
+    assert err32 <= 2.0 ** -19
+    probs = [p, api.Problem(31, 11, -8.0, 8.0, 8.0, F=0.7, eps=0.1), p.with_(precision="fp32")]
+    us = [dev(u), dev(inputs.smooth_state(31, 11, 0.05, 7)), dev(u)]
+    single = [host(api.residual(q, v)) for q, v in zip(probs, us)]
+    batched = [host(e) for e in api.residual_batched(probs, us)]
+    for a, b in zip(single, batched):
+        assert np.array_equal(a, b)
+
+
+def test_wide_meshes_are_refused_where_a_preconditioner_is_needed():
+    """Beyond N = 1024 the residual, JVP and zeta work, but the preconditioner (its
+    apply holds a block row in LDS) and therefore a solve refuse the mesh."""
+    p = api.Problem(1100, 5, -20.0, 20.0, 2.0, F=0.7, eps=0.2)
+    with pytest.raises(Exception, match="1024"):
+        api.Preconditioner(p, 1)
+    with pytest.raises(Exception, match="1024"):
+        api.solve(p.F, p.eps, p.N, p.M, p.x1, p.xN, p.yM)
+
+
 def test_fp32_flat_state_without_source_is_exactly_zero():
     p = gprob(inputs.W31X11, eps=0.0, precision="fp32")
     E = gpu_residual(p, inputs.flat_state(p.N, p.M))

@@ -166,7 +166,7 @@ def test_preconditioner_wide_blocks_match_dense_solve(N, M):
     either side of N = 182), the column-strip launches up to N = 256, and beyond that
     the panel and update launches with 2 and 4 panel rows per thread.  From N = 667 the
     substitution runs one block row per step (no super rows), the path of 721 x 241;
-    N = 1024 is the largest mesh width the library accepts."""
+    N = 1024 is the largest mesh width that a preconditioner accepts."""
     p = api.Problem(N, M, -10.0, 8.0, 3.0, F=0.75, eps=0.1)
     op = oprob(p)
     b = np.random.default_rng(N).standard_normal(p.n_unknowns)

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SHIPWAVE_ABI_VERSION 2
+#define SHIPWAVE_ABI_VERSION 3
 
 enum {
     SW_OK = 0,
@@ -154,6 +154,20 @@ int32_t shipwave_precond_build_banded(const sw_problem* prob, int32_t q_blocks, 
  * 2NM doubles; may alias.  The handle owns the apply's temporaries, so applies
  * of one handle must not run concurrently on different streams. */
 int32_t shipwave_precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t stream);
+/* x_i = P_i^{-1} b_i for n requests, each the three-step block solve of Appendix C as
+ * in shipwave_precond_apply, with the steps of several requests sharing launches:
+ * requests whose handles use super-row substitution (block widths N up to a few
+ * hundred) run in rounds of distinct handles, one launch per step for the whole round
+ * (the first step, step k of every request's substitution, the last step); any other
+ * request, and a round of one, runs as shipwave_precond_apply.  Requests that share a
+ * handle go in different rounds, since the handle owns the temporaries.  P: host array
+ * of n handles; b, x: host arrays of n device pointers (2NM doubles each; b_i may
+ * alias x_i; the vectors of different requests must not overlap).  Each x_i is bitwise
+ * the result of shipwave_precond_apply on that request alone.  Null pointers or n < 0
+ * return SW_EINVAL. */
+int32_t shipwave_precond_apply_batched(int32_t n, const sw_precond* const* P,
+                                       const double* const* b, double* const* x,
+                                       hipStream_t stream);
 void shipwave_precond_destroy(sw_precond* P);
 
 typedef struct {

@@ -77,6 +77,7 @@ SIGNATURES = {
     "shipwave_jvp": (I32, [C.POINTER(SwProblem), P, P, P, D, P, P]),
     "shipwave_precond_build_banded": (I32, [C.POINTER(SwProblem), I32, C.POINTER(P), P]),
     "shipwave_precond_apply": (I32, [P, P, P, P]),
+    "shipwave_precond_apply_batched": (I32, [I32, C.POINTER(P), C.POINTER(P), C.POINTER(P), P]),
     "shipwave_precond_destroy": (None, [P]),
     "shipwave_solve_opts_default": (None, [C.POINTER(SwSolveOpts)]),
     "shipwave_solve": (I32, [D, D, C.POINTER(SwMesh), C.POINTER(SwDomain),

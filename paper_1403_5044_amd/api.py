@@ -172,6 +172,19 @@ class Preconditioner:
                                                 _stream()))
         return out
 
+    @staticmethod
+    def apply_batched(pcs, bs, outs=None):
+        """x_i = P_i^{-1} b_i for several preconditioners in shared launches."""
+        n = len(pcs)
+        if outs is None:
+            outs = [torch.empty(p.prob.n_unknowns, dtype=torch.float64, device=b.device)
+                    for p, b in zip(pcs, bs)]
+        hp = (C.c_void_p * n)(*[p.handle.value for p in pcs])
+        bp = (C.c_void_p * n)(*[_dev(b, p.prob.n_unknowns, "b") for p, b in zip(pcs, bs)])
+        xp = (C.c_void_p * n)(*[_dev(x, p.prob.n_unknowns, "x") for p, x in zip(pcs, outs)])
+        L.check(_lib().shipwave_precond_apply_batched(n, hp, bp, xp, _stream()))
+        return outs
+
     def close(self):
         if self.handle:
             torch.cuda.current_stream().synchronize()

@@ -79,6 +79,7 @@ struct sw_precond {
     int sb = 0;                      // block rows per super row (0: one block row per step)
     double* W = nullptr;             // super-row operators (nonzero N x N blocks)
     std::vector<sw::SuperStep> fsteps, bsteps;  // kernel arguments of the super-row steps
+    sw::SuperStep* dsteps = nullptr;            // device copy: fsteps, then bsteps
     std::vector<sw::BandStep> band_steps;       // forward then backward steps when sb <= 1
     std::vector<int> ord;                       // elimination order of the block rows
     size_t bytes = 0;
@@ -1326,12 +1327,11 @@ __device__ void lds_trapezoid(const Geo& g, const double* v, double* z) {
     lds_prefix_sum(z, N);
 }
 
-// s1 = A-hat^{-1} b1, t2 = b2 - 2 pi T s1 (per row l)
-__global__ __launch_bounds__(64) void k_apply_first(Geo g, const double* __restrict__ b,
-                                                    double* __restrict__ s1,
-                                                    double* __restrict__ t2) {
+// s1 = A-hat^{-1} b1, t2 = b2 - 2 pi T s1 (row l)
+__device__ __forceinline__ void apply_first_row(const Geo& g, const double* __restrict__ b,
+                                                double* __restrict__ s1,
+                                                double* __restrict__ t2, int l) {
     __shared__ double B[kMaxN], X[kMaxN], Z[kMaxN];
-    const int l = blockIdx.x;
     const int N = g.N;
     const size_t o = (size_t)l * N;
     for (int i = threadIdx.x; i < N; i += 64) B[i] = b[o + i];
@@ -1344,12 +1344,11 @@ __global__ __launch_bounds__(64) void k_apply_first(Geo g, const double* __restr
         t2[o + i] = b2[i] - ((i == 0) ? 0.0 : kTwoPi * 0.5 * (Z[i - 1] + Z[i]));
 }
 
-// r1 = s1 - A-hat^{-1} (T s2 / F^2), r2 = s2 (per row l)
-__global__ __launch_bounds__(64) void k_apply_last(Geo g, const double* __restrict__ s1,
-                                                   const double* __restrict__ s2,
-                                                   double* __restrict__ x) {
+// r1 = s1 - A-hat^{-1} (T s2 / F^2), r2 = s2 (row l)
+__device__ __forceinline__ void apply_last_row(const Geo& g, const double* __restrict__ s1,
+                                               const double* __restrict__ s2,
+                                               double* __restrict__ x, int l) {
     __shared__ double V[kMaxN], Z[kMaxN], X[kMaxN];
-    const int l = blockIdx.x;
     const int N = g.N;
     const size_t o = (size_t)l * N;
     for (int i = threadIdx.x; i < N; i += 64) V[i] = s2[o + i];
@@ -1363,6 +1362,50 @@ __global__ __launch_bounds__(64) void k_apply_last(Geo g, const double* __restri
     __syncthreads();
     lds_ahat_solve(g, V, X);
     for (int i = threadIdx.x; i < N; i += 64) x[o + i] = s1[o + i] - X[i];
+}
+
+__global__ __launch_bounds__(64) void k_apply_first(Geo g, const double* __restrict__ b,
+                                                    double* __restrict__ s1,
+                                                    double* __restrict__ t2) {
+    apply_first_row(g, b, s1, t2, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_apply_last(Geo g, const double* __restrict__ s1,
+                                                   const double* __restrict__ s2,
+                                                   double* __restrict__ x) {
+    apply_last_row(g, s1, s2, x, blockIdx.x);
+}
+
+// First or last step of several applies in one launch: workgroups [first[p], first[p+1])
+// take the block rows of request p, whose temporaries are work[p] (the handle's [4][NM]).
+constexpr int kMaxApplyBatch = 24;
+struct ApplyBatch {
+    Geo g[kMaxApplyBatch];
+    double* work[kMaxApplyBatch];
+    const double* in[kMaxApplyBatch];  // b (first step)
+    double* out[kMaxApplyBatch];       // x (last step)
+    int first[kMaxApplyBatch + 1];
+    int n;
+};
+static_assert(sizeof(ApplyBatch) <= 4096, "kernel argument block");
+
+__device__ __forceinline__ int batch_member(const int* first, int n) {
+    int p = 0;
+    while (p + 1 < n && (int)blockIdx.x >= first[p + 1]) ++p;
+    return p;
+}
+
+__global__ __launch_bounds__(64) void k_apply_first_batched(const ApplyBatch ab) {
+    const int p = batch_member(ab.first, ab.n);
+    const Geo& g = ab.g[p];
+    apply_first_row(g, ab.in[p], ab.work[p], ab.work[p] + g.NM, blockIdx.x - ab.first[p]);
+}
+
+__global__ __launch_bounds__(64) void k_apply_last_batched(const ApplyBatch ab) {
+    const int p = batch_member(ab.first, ab.n);
+    const Geo& g = ab.g[p];
+    apply_last_row(g, ab.work[p], ab.work[p] + 2 * (size_t)g.NM, ab.out[p],
+                   blockIdx.x - ab.first[p]);
 }
 
 // One wavefront per output row r of one block row:
@@ -1549,8 +1592,7 @@ __global__ __launch_bounds__(256) void k_blockdiag_gemv(int N, int M, const doub
 // One workgroup per output row of a super-row step (SuperStep): its four wavefronts
 // take every fourth term, so that each has few dependent load rounds, and the four
 // partial dot products are added in a fixed order.
-__global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st) {
-    const int row = blockIdx.x;
+__device__ __forceinline__ void super_step_row(int N, const SuperStep& st, int row) {
     const int i = row / N, r = row - i * N;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int t0 = st.first[i], t1 = st.first[i + 1];
@@ -1577,6 +1619,25 @@ __global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st) {
     if (lane == 0) part[w] = sum;
     __syncthreads();
     if (threadIdx.x == 0) st.out[i][r] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+__global__ __launch_bounds__(256) void k_super_step(int N, const SuperStep st) {
+    super_step_row(N, st, blockIdx.x);
+}
+
+// Step k of several applies in one launch: request p's step descriptor is st[p] (device
+// copy of the handle's kernel arguments), its nrow N rows workgroups [first[p], first[p+1]).
+struct StepBatch {
+    const SuperStep* st[kMaxApplyBatch];
+    int N[kMaxApplyBatch];
+    int first[kMaxApplyBatch + 1];
+    int n;
+};
+static_assert(sizeof(StepBatch) <= 4096, "kernel argument block");
+
+__global__ __launch_bounds__(256) void k_super_step_batched(const StepBatch sb) {
+    const int p = batch_member(sb.first, sb.n);
+    super_step_row(sb.N[p], *sb.st[p], blockIdx.x - sb.first[p]);
 }
 
 // dst = 0, I, src or -src for a batch of N x N blocks; grid (chunks, jobs)
@@ -2272,6 +2333,12 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         if (q > 0 && P->sb > 1) {
             super_steps(P, plan);
             capture_substitution(P);
+            std::vector<SuperStep> all(P->fsteps);
+            all.insert(all.end(), P->bsteps.begin(), P->bsteps.end());
+            SW_HIP(hipMalloc(&P->dsteps, all.size() * sizeof(SuperStep)));
+            SW_HIP(hipMemcpyAsync(P->dsteps, all.data(), all.size() * sizeof(SuperStep),
+                                  hipMemcpyHostToDevice, s));
+            SW_HIP(hipStreamSynchronize(s));
         } else if (q > 0) {
             std::vector<GemvTerm> tv;
             double* tmpv = P->work + 3 * NM;
@@ -2320,6 +2387,7 @@ sw_precond* precond_build(const Geo& g0, int q_req, hipStream_t s) {
         (void)hipStreamSynchronize(s);
         precond_release(P->base, P->block, P->device);
         if (P->terms) (void)hipFree(P->terms);
+        if (P->dsteps) (void)hipFree(P->dsteps);
         if (P->subst) (void)hipGraphExecDestroy(P->subst);
         delete P;
         throw;
@@ -2472,6 +2540,72 @@ void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t 
     SW_HIP(hipGetLastError());
 }
 
+// Applies of several handles in shared launches.  Handles with super-row substitution
+// go in rounds of distinct handles (a handle holds its apply's temporaries): one launch
+// for the first step of every request in the round, then launch k runs step k of every
+// request that has one (a request's steps: its forward steps, then its backward steps),
+// then one launch for the last step.  Each request runs the same per-row arithmetic as
+// precond_apply, so its result has the same bits.  A round of one request, and every
+// other handle, goes through precond_apply.
+void precond_apply_batched(int n, const sw_precond* const* P, const double* const* b,
+                           double* const* x, hipStream_t s) {
+    std::vector<int> pending;
+    for (int i = 0; i < n; ++i) {
+        if (P[i]->q > 0 && P[i]->sb > 1 && P[i]->dsteps)
+            pending.push_back(i);
+        else
+            precond_apply(P[i], b[i], x[i], s);
+    }
+    while (!pending.empty()) {
+        std::vector<int> round, later;
+        for (int i : pending) {
+            bool dup = (int)round.size() >= kMaxApplyBatch;
+            for (int j : round) dup = dup || P[j] == P[i];
+            (dup ? later : round).push_back(i);
+        }
+        pending.swap(later);
+        if (round.size() == 1) {
+            precond_apply(P[round[0]], b[round[0]], x[round[0]], s);
+            continue;
+        }
+        const int nr = (int)round.size();
+        ApplyBatch ab{};
+        int rows = 0, nsteps = 0;
+        for (int k = 0; k < nr; ++k) {
+            const sw_precond* Q = P[round[k]];
+            ab.g[k] = Q->g;
+            ab.work[k] = Q->work;
+            ab.in[k] = b[round[k]];
+            ab.out[k] = x[round[k]];
+            ab.first[k] = rows;
+            rows += Q->g.M;
+            nsteps = std::max(nsteps, (int)(Q->fsteps.size() + Q->bsteps.size()));
+        }
+        ab.first[nr] = rows;
+        ab.n = nr;
+        k_apply_first_batched<<<rows, 64, 0, s>>>(ab);
+        for (int t = 0; t < nsteps; ++t) {
+            StepBatch sb{};
+            int wg = 0;
+            for (int k = 0; k < nr; ++k) {
+                const sw_precond* Q = P[round[k]];
+                const int nf = (int)Q->fsteps.size();
+                if (t >= nf + (int)Q->bsteps.size()) continue;
+                const SuperStep& hs = (t < nf) ? Q->fsteps[t] : Q->bsteps[t - nf];
+                sb.st[sb.n] = Q->dsteps + t;
+                sb.N[sb.n] = Q->g.N;
+                sb.first[sb.n] = wg;
+                wg += hs.nrow * Q->g.N;
+                ++sb.n;
+            }
+            sb.first[sb.n] = wg;
+            k_super_step_batched<<<wg, 256, 0, s>>>(sb);
+        }
+        k_apply_last_batched<<<rows, 64, 0, s>>>(ab);
+        SW_HIP(hipGetLastError());
+    }
+}
+
 void precond_destroy(sw_precond* P, bool keep_block) {
     if (!P) return;
     int cur = -1;
@@ -2483,6 +2617,7 @@ void precond_destroy(sw_precond* P, bool keep_block) {
     else
         (void)hipFree(P->base);
     if (P->terms) (void)hipFree(P->terms);
+    if (P->dsteps) (void)hipFree(P->dsteps);
     if (P->subst) (void)hipGraphExecDestroy(P->subst);
     if (P->device >= 0 && P->device != cur) (void)hipSetDevice(cur);
     delete P;
@@ -2510,6 +2645,18 @@ int32_t shipwave_precond_apply(const sw_precond* P, const double* b, double* x,
     return guard([&]() -> int32_t {
         SW_REQUIRE(P && b && x, "null pointer");
         precond_apply(P, b, x, stream);
+        return SW_OK;
+    });
+}
+
+int32_t shipwave_precond_apply_batched(int32_t n, const sw_precond* const* P,
+                                       const double* const* b, double* const* x,
+                                       hipStream_t stream) {
+    return guard([&]() -> int32_t {
+        SW_REQUIRE(n >= 0, "n must be >= 0");
+        SW_REQUIRE(n == 0 || (P && b && x), "null pointer");
+        for (int i = 0; i < n; ++i) SW_REQUIRE(P[i] && b[i] && x[i], "null pointer");
+        precond_apply_batched(n, P, b, x, stream);
         return SW_OK;
     });
 }

@@ -151,6 +151,7 @@ void sw_server::start_task(Active& a, int precision) {
     a.zeta = c.take<double>((size_t)a.g.NM);
     void* tmem = c.p + ((c.off + 255) & ~size_t(255));
     a.task.reset(new SolveTask(a.g, a.prm, a.P, a.u, tmem, a.pin));
+    a.task->defer_apply = true;
 }
 
 namespace {
@@ -313,8 +314,22 @@ void sw_server::run() {
             std::vector<Geo> geos;
             std::vector<const double*> xs;
             std::vector<double*> Es;
+            // Krylov steps stop at their preconditioner applies, which run together
+            std::vector<const sw_precond*> aP;
+            std::vector<const double*> ab;
+            std::vector<double*> ax;
             for (auto& a : active) {
                 a->task->pre(stream);
+                if (a->task->apply_pending) {
+                    aP.push_back(a->task->apply_P);
+                    ab.push_back(a->task->apply_b);
+                    ax.push_back(a->task->apply_x);
+                }
+            }
+            if (!aP.empty())
+                precond_apply_batched((int)aP.size(), aP.data(), ab.data(), ax.data(), stream);
+            for (auto& a : active) {
+                if (a->task->apply_pending) a->task->pre_rest(stream);
                 if (a->task->done()) continue;
                 geos.push_back(*a->task->req_g);
                 xs.push_back(a->task->req_x);

@@ -140,12 +140,18 @@ void SolveTask::pre(hipStream_t s) {
             } else if (pending_scale_ > 0.0) {
                 scale_copy(n_, 1.0 / pending_scale_, vj, vj, s);
             }
+            if (defer_apply) {
+                apply_pending = true;
+                apply_P = P_;
+                apply_b = vj;
+                apply_x = z_;
+                req_x = nullptr;
+                req_E = nullptr;
+                req_g = nullptr;
+                return;
+            }
             precond_apply(P_, vj, z_, s);
-            shift_auto(n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
-                       hd_ + 2 * m + 8, xs_, red_, s);
-            req_x = xs_;
-            req_E = Ejv_;
-            req_g = &gin_;
+            pre_rest(s);
             break;
         }
         case Phase::Restart:
@@ -172,6 +178,17 @@ void SolveTask::pre(hipStream_t s) {
             req_g = nullptr;
             break;
     }
+}
+
+// the rest of a Krylov step's pre() once z = P^{-1} v_j is enqueued: the shifted state
+void SolveTask::pre_rest(hipStream_t s) {
+    const int m = m_;
+    apply_pending = false;
+    shift_auto(n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
+               hd_ + 2 * m + 8, xs_, red_, s);
+    req_x = xs_;
+    req_E = Ejv_;
+    req_g = &gin_;
 }
 
 void SolveTask::maybe_inject(int kind, hipStream_t s) {

@@ -2,6 +2,9 @@
 // evaluation is an explicit request.  A driver calls, per step,
 //   pre(s)   enqueue the device work that produces the next state to evaluate
 //            (req_x) and names the output (req_E) and the precision (req_g);
+//            with defer_apply set, a Krylov step stops at its preconditioner apply
+//            and names it in apply_P/apply_b/apply_x (apply_pending); the driver
+//            runs it, alone or batched with other tasks', then calls pre_rest(s);
 //   <evaluate E(req_x) -> req_E, alone or batched with other tasks>;
 //   post(s)  enqueue the device work that consumes req_E and copies the
 //            scalars the host needs into pinned memory;
@@ -20,6 +23,9 @@ namespace sw {
 
 sw_precond* precond_build(const Geo& g, int q, hipStream_t s);
 void precond_apply(const sw_precond* P, const double* b, double* x, hipStream_t s);
+// x_i = P_i^{-1} b_i for n requests in shared launches; bitwise precond_apply on each
+void precond_apply_batched(int n, const sw_precond* const* P, const double* const* b,
+                           double* const* x, hipStream_t s);
 // keep_block: the device block may be kept for the next set-up of a similar size
 // (otherwise it is freed at once)
 void precond_destroy(sw_precond* P, bool keep_block = true);
@@ -65,12 +71,19 @@ class SolveTask {
     // the preconditioner may be supplied after construction, before the first Krylov step
     void set_precond(const sw_precond* P) { P_ = P; }
     void pre(hipStream_t s);
+    void pre_rest(hipStream_t s);
     void post(hipStream_t s);
     void host(hipStream_t s);
 
     const double* req_x = nullptr;
     double* req_E = nullptr;
     const Geo* req_g = nullptr;
+
+    bool defer_apply = false;
+    bool apply_pending = false;
+    const sw_precond* apply_P = nullptr;
+    const double* apply_b = nullptr;
+    double* apply_x = nullptr;
 
     int status = SW_ENOCONV;
     int newton = 0;

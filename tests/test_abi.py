@@ -34,7 +34,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     lib = _lib.load()
-    assert lib.shipwave_abi_version() == 2
+    assert lib.shipwave_abi_version() == 3
     assert isinstance(lib.shipwave_last_error(), bytes)
 
 

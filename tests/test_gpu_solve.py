@@ -57,6 +57,37 @@ def test_preconditioner_apply_in_place():
     P.close()
 
 
+def test_batched_apply_is_bitwise_the_single_apply():
+    """Several preconditioners applied in shared launches give the bits of one apply each:
+    super-row handles of different widths in one round, a handle used twice (second
+    round), q = 0 and a one-block-row band (N = 700) through the single path, an
+    in-place request, and 25 distinct handles (a full round of 24, then a round of 1)."""
+    dom = dict(x1=-16.0, xN=8.0, yM=12.0)
+    pcs = [api.Preconditioner(api.Problem(61, 21, **dom, F=0.7, eps=0.1), 3),
+           api.Preconditioner(api.Problem(121, 41, **dom, F=0.9, eps=0.1), 5),
+           api.Preconditioner(api.Problem(31, 11, -8.0, 8.0, 8.0, F=0.6, eps=0.1), 0),
+           api.Preconditioner(api.Problem(700, 9, -14.0, 40.0, 6.0, F=0.7, eps=0.1), 2),
+           api.Preconditioner(api.Problem(41, 13, -8.0, 8.0, 6.0, F=0.9, eps=0.1,
+                                          weights="simpson"), 2)]
+    small = [api.Preconditioner(api.Problem(13, 5, -4.0, 4.0, 3.0, F=0.5 + 0.02 * k,
+                                            eps=0.1), 1 + k % 3) for k in range(25)]
+    rng = np.random.default_rng(11)
+    for reqs in ([0, 1, 0, 2, 3, 4, 1], list(range(len(pcs), len(pcs) + 25))):
+        allp = pcs + small
+        sel = [allp[i] for i in reqs]
+        bs = [dev(rng.standard_normal(P.prob.n_unknowns)) for P in sel]
+        single = [host(P.apply(b)) for P, b in zip(sel, bs)]
+        outs = [torch.empty_like(b) for b in bs]
+        outs[-1] = bs[-1].clone()
+        bs[-1] = outs[-1]  # in place
+        got = [host(x) for x in api.Preconditioner.apply_batched(sel, bs, outs)]
+        for i, (a, g) in enumerate(zip(single, got)):
+            assert np.array_equal(a, g), (reqs[i], sel[i].prob.N, sel[i].prob.M, sel[i].q)
+        log(f"batched apply of {len(sel)} requests: bitwise equal")
+    for P in pcs + small:
+        P.close()
+
+
 def _oracle_root(p, tol=1e-12):
     op = oprob(p)
     u, info = newton(op, oflat(op), tol=tol)

@@ -4,13 +4,16 @@
 // result is bitwise reproducible.
 #include "sw_internal.hpp"
 
+#include <algorithm>
+#include <vector>
+
 namespace sw {
 
 namespace {
 
 constexpr int kThreads = 256;
 
-inline int red_blocks(int n) {
+__host__ __device__ inline int red_blocks(int n) {
     int b = (n + kThreads * 4 - 1) / (kThreads * 4);
     return b < 1 ? 1 : (b > 512 ? 512 : b);
 }
@@ -53,17 +56,23 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 }
 
 // work[i * B + b] = partial dot of V_i and w over the block's grid-stride range
+__device__ __forceinline__ void dots1_body(int n, const double* __restrict__ V, size_t ldv,
+                                           const double* __restrict__ w,
+                                           double* __restrict__ work, int bx, int i, int nbx,
+                                           double* sh) {
+    const double* v = V + (size_t)i * ldv;
+    double s = 0.0;
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads)
+        s = fma(v[t], w[t], s);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) work[(size_t)i * nbx + bx] = s;
+}
+
 __global__ __launch_bounds__(kThreads) void k_dots1(int n, const double* __restrict__ V,
                                                     size_t ldv, const double* __restrict__ w,
                                                     double* __restrict__ work) {
     __shared__ double sh[kThreads / 64];
-    const int i = blockIdx.y;
-    const double* v = V + (size_t)i * ldv;
-    double s = 0.0;
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
-        s = fma(v[t], w[t], s);
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) work[(size_t)i * gridDim.x + blockIdx.x] = s;
+    dots1_body(n, V, ldv, w, work, blockIdx.x, blockIdx.y, gridDim.x, sh);
 }
 
 __global__ void k_dots2(int k, int B, const double* __restrict__ work, double* __restrict__ out) {
@@ -94,11 +103,14 @@ __global__ __launch_bounds__(kThreads) void k_gemv_acc(int n, int k, const doubl
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_norm1(int n, const double* __restrict__ x,
-                                                    double* __restrict__ work) {
-    __shared__ double sh[kThreads / 64];
+// The kernels below are written as bodies over block bx of nbx blocks, so that the
+// batched launches (several independent vectors, each over its own range of blocks)
+// run the same arithmetic in the same order as the single launches.
+__device__ __forceinline__ void norm1_body(int n, const double* __restrict__ x,
+                                           double* __restrict__ work, int bx, int nbx,
+                                           double* sh) {
     double m = 0.0, s = 0.0;
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads) {
         const double v = x[t];
         // NaN propagates through the sum of squares; fmax would drop it
         m = fmax(m, fabs(v));
@@ -107,13 +119,20 @@ __global__ __launch_bounds__(kThreads) void k_norm1(int n, const double* __restr
     m = block_max(m, sh);
     s = block_sum(s, sh);
     if (threadIdx.x == 0) {
-        work[blockIdx.x] = m;
-        work[gridDim.x + blockIdx.x] = s;
+        work[bx] = m;
+        work[nbx + bx] = s;
     }
 }
 
-__global__ void k_norm2(int B, const double* __restrict__ work, double* __restrict__ out2) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kThreads) void k_norm1(int n, const double* __restrict__ x,
+                                                    double* __restrict__ work) {
+    __shared__ double sh[kThreads / 64];
+    norm1_body(n, x, work, blockIdx.x, gridDim.x, sh);
+}
+
+// thread 0 only
+__device__ __forceinline__ void norm2_body(int B, const double* __restrict__ work,
+                                           double* __restrict__ out2) {
     double m = 0.0, s = 0.0;
     for (int b = 0; b < B; ++b) {
         m = fmax(m, work[b]);
@@ -122,6 +141,11 @@ __global__ void k_norm2(int B, const double* __restrict__ work, double* __restri
     // a non-finite sum of squares marks the max norm as non-finite too
     out2[0] = (s == s && s <= 1.7976931348623157e308) ? m : s;
     out2[1] = sqrt(s);
+}
+
+__global__ void k_norm2(int B, const double* __restrict__ work, double* __restrict__ out2) {
+    if (threadIdx.x != 0) return;
+    norm2_body(B, work, out2);
 }
 
 __global__ void k_jvp_h(const double* norms_u, const double* norms_z, double sqrt_eps,
@@ -167,15 +191,14 @@ __global__ __launch_bounds__(kThreads) void k_quot(int n, const double* __restri
 
 // Final pass of norm_inf_2 on z (partials in work), the JVP step from it (as k_jvp_h),
 // and out = u + step z.  Workgroup 0 stores the norms of z and h = [step, 1/step].
-__global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B,
-                                                         const double* __restrict__ work,
-                                                         const double* __restrict__ norms_u,
-                                                         double sqrt_eps, double sqrt_n,
-                                                         double* __restrict__ norms_z,
-                                                         double* __restrict__ h,
-                                                         const double* __restrict__ u,
-                                                         const double* __restrict__ z,
-                                                         double* __restrict__ out) {
+__device__ __forceinline__ void shift_auto_body(int n, int B, const double* __restrict__ work,
+                                                const double* __restrict__ norms_u,
+                                                double sqrt_eps, double sqrt_n,
+                                                double* __restrict__ norms_z,
+                                                double* __restrict__ h,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ z,
+                                                double* __restrict__ out, int bx, int nbx) {
     __shared__ double st_s;
     if (threadIdx.x == 0) {
         double m = 0.0, s = 0.0;
@@ -190,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B,
             inv = 1.0 / st;
         }
         st_s = st;
-        if (blockIdx.x == 0) {
+        if (bx == 0) {
             norms_z[0] = (s == s && s <= 1.7976931348623157e308) ? m : s;
             norms_z[1] = nz;
             h[0] = st;
@@ -199,12 +222,44 @@ __global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B,
     }
     __syncthreads();
     const double st = st_s;
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads)
         out[t] = fma(st, z[t], u[t]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_shift_auto(int n, int B,
+                                                         const double* __restrict__ work,
+                                                         const double* __restrict__ norms_u,
+                                                         double sqrt_eps, double sqrt_n,
+                                                         double* __restrict__ norms_z,
+                                                         double* __restrict__ h,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ z,
+                                                         double* __restrict__ out) {
+    shift_auto_body(n, B, work, norms_u, sqrt_eps, sqrt_n, norms_z, h, u, z, out, blockIdx.x,
+                    gridDim.x);
 }
 
 // w = (Ep - Eu) / step (as k_quot; stored by the blocks of V_0) and the partial dots of
 // V_i with it (as k_dots1).
+__device__ __forceinline__ void dots1_quot_body(int n, const double* __restrict__ V, size_t ldv,
+                                                const double* __restrict__ Ep,
+                                                const double* __restrict__ Eu,
+                                                const double* __restrict__ h,
+                                                double* __restrict__ w,
+                                                double* __restrict__ work, int bx, int i,
+                                                int nbx, double* sh) {
+    const double* v = V + (size_t)i * ldv;
+    const double r = h[1];
+    double s = 0.0;
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads) {
+        const double wt = (Ep[t] - Eu[t]) * r;
+        if (i == 0) w[t] = wt;
+        s = fma(v[t], wt, s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) work[(size_t)i * nbx + bx] = s;
+}
+
 __global__ __launch_bounds__(kThreads) void k_dots1_quot(int n, const double* __restrict__ V,
                                                          size_t ldv, const double* __restrict__ Ep,
                                                          const double* __restrict__ Eu,
@@ -212,21 +267,31 @@ __global__ __launch_bounds__(kThreads) void k_dots1_quot(int n, const double* __
                                                          double* __restrict__ w,
                                                          double* __restrict__ work) {
     __shared__ double sh[kThreads / 64];
-    const int i = blockIdx.y;
-    const double* v = V + (size_t)i * ldv;
-    const double r = h[1];
-    double s = 0.0;
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
-        const double wt = (Ep[t] - Eu[t]) * r;
-        if (i == 0) w[t] = wt;
-        s = fma(v[t], wt, s);
-    }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) work[(size_t)i * gridDim.x + blockIdx.x] = s;
+    dots1_quot_body(n, V, ldv, Ep, Eu, h, w, work, blockIdx.x, blockIdx.y, gridDim.x, sh);
 }
 
 // Final pass of dots (partials in work, B per vector) in every block, then
 // w -= sum_i h[i] V_i (as k_gemv_sub).  Block 0 stores h.
+__device__ __forceinline__ void gemv_sub_dots_body(int n, int k, int B,
+                                                   const double* __restrict__ V, size_t ldv,
+                                                   const double* __restrict__ work,
+                                                   double* __restrict__ hout,
+                                                   double* __restrict__ w, int bx, int nbx,
+                                                   double* hs) {
+    for (int i = threadIdx.x; i < k; i += kThreads) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += work[(size_t)i * B + b];
+        hs[i] = s;
+        if (bx == 0) hout[i] = s;
+    }
+    __syncthreads();
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads) {
+        double s = w[t];
+        for (int i = 0; i < k; ++i) s = fma(-hs[i], V[(size_t)i * ldv + t], s);
+        w[t] = s;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_gemv_sub_dots(int n, int k, int B,
                                                             const double* __restrict__ V,
                                                             size_t ldv,
@@ -234,18 +299,110 @@ __global__ __launch_bounds__(kThreads) void k_gemv_sub_dots(int n, int k, int B,
                                                             double* __restrict__ hout,
                                                             double* __restrict__ w) {
     extern __shared__ double hs[];
-    for (int i = threadIdx.x; i < k; i += kThreads) {
-        double s = 0.0;
-        for (int b = 0; b < B; ++b) s += work[(size_t)i * B + b];
-        hs[i] = s;
-        if (blockIdx.x == 0) hout[i] = s;
-    }
-    __syncthreads();
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads) {
-        double s = w[t];
-        for (int i = 0; i < k; ++i) s = fma(-hs[i], V[(size_t)i * ldv + t], s);
-        w[t] = s;
-    }
+    gemv_sub_dots_body(n, k, B, V, ldv, work, hout, w, blockIdx.x, gridDim.x, hs);
+}
+
+// ---- batched forms: job p takes blocks [first[p], first[p + 1]) of a 1-D grid ----
+constexpr int kMaxKJobs = 16;
+
+__device__ __forceinline__ int job_of(const int* first, int nj) {
+    int p = 0;
+    while (p + 1 < nj && (int)blockIdx.x >= first[p + 1]) ++p;
+    return p;
+}
+
+struct NormJob {
+    int n;
+    const double* x;
+    double* work;
+    double* out2;
+};
+struct NormBatch {
+    NormJob j[kMaxKJobs];
+    int first[kMaxKJobs + 1];
+    int nj;
+};
+
+struct ShiftJob {
+    int n, B;
+    const double* work;
+    const double* norms_u;
+    double* norms_z;
+    double* h;
+    const double* u;
+    const double* z;
+    double* out;
+    double sqrt_eps, sqrt_n;
+};
+struct ShiftBatch {
+    ShiftJob j[kMaxKJobs];
+    int first[kMaxKJobs + 1];
+    int nj;
+};
+
+struct CgsJob {
+    int n, k, B;
+    const double* V;
+    size_t ldv;
+    const double* Ep;  // first pass: w = (Ep - Eu) / h[0]; nullptr: w as it is
+    const double* Eu;
+    const double* h;
+    double* w;
+    double* hout;
+    double* work;
+};
+struct CgsBatch {
+    CgsJob j[kMaxKJobs];
+    int first[kMaxKJobs + 1];
+    int nj;
+};
+static_assert(sizeof(NormBatch) <= 4096 && sizeof(ShiftBatch) <= 4096 &&
+                  sizeof(CgsBatch) <= 4096,
+              "kernel argument block");
+
+// blocks per job: red_blocks(n)
+__global__ __launch_bounds__(kThreads) void k_norm1_batched(const NormBatch b) {
+    __shared__ double sh[kThreads / 64];
+    const int p = job_of(b.first, b.nj);
+    const NormJob& J = b.j[p];
+    norm1_body(J.n, J.x, J.work, blockIdx.x - b.first[p], b.first[p + 1] - b.first[p], sh);
+}
+
+// one block per job
+__global__ void k_norm2_batched(const NormBatch b) {
+    if (threadIdx.x != 0) return;
+    const NormJob& J = b.j[blockIdx.x];
+    norm2_body(red_blocks(J.n), J.work, J.out2);
+}
+
+// blocks per job: ew_blocks(n)
+__global__ __launch_bounds__(kThreads) void k_shift_auto_batched(const ShiftBatch b) {
+    const int p = job_of(b.first, b.nj);
+    const ShiftJob& J = b.j[p];
+    shift_auto_body(J.n, J.B, J.work, J.norms_u, J.sqrt_eps, J.sqrt_n, J.norms_z, J.h, J.u, J.z,
+                    J.out, blockIdx.x - b.first[p], b.first[p + 1] - b.first[p]);
+}
+
+// blocks per job: B k, block l of the job is (l % B, vector l / B)
+__global__ __launch_bounds__(kThreads) void k_dots1_batched(const CgsBatch b) {
+    __shared__ double sh[kThreads / 64];
+    const int p = job_of(b.first, b.nj);
+    const CgsJob& J = b.j[p];
+    const int l = blockIdx.x - b.first[p];
+    const int i = l / J.B, bx = l - i * J.B;
+    if (J.Ep)
+        dots1_quot_body(J.n, J.V, J.ldv, J.Ep, J.Eu, J.h, J.w, J.work, bx, i, J.B, sh);
+    else
+        dots1_body(J.n, J.V, J.ldv, J.w, J.work, bx, i, J.B, sh);
+}
+
+// blocks per job: ew_blocks(n); dynamic LDS: the largest k
+__global__ __launch_bounds__(kThreads) void k_gemv_sub_dots_batched(const CgsBatch b) {
+    extern __shared__ double hs[];
+    const int p = job_of(b.first, b.nj);
+    const CgsJob& J = b.j[p];
+    gemv_sub_dots_body(J.n, J.k, J.B, J.V, J.ldv, J.work, J.hout, J.w, blockIdx.x - b.first[p],
+                       b.first[p + 1] - b.first[p], hs);
 }
 
 __global__ void k_flat(int NM, double* u) {
@@ -361,6 +518,91 @@ void cgs_pass(int n, int k, const double* V, size_t ldv, const double* w_in_Ep,
     } else {
         k_dots2<<<(k + 63) / 64, 64, 0, s>>>(k, B, work, hout);
         k_gemv_sub<<<ew_blocks(n), kThreads, 0, s>>>(n, k, V, ldv, hout, w);
+    }
+}
+
+void shift_auto_batched(int nj, const ShiftArgs* a, hipStream_t s) {
+    for (int o = 0; o < nj; o += kMaxKJobs) {
+        const int c = std::min(kMaxKJobs, nj - o);
+        NormBatch nb{};
+        ShiftBatch sb{};
+        int rb = 0, eb = 0;
+        for (int q = 0; q < c; ++q) {
+            const ShiftArgs& A = a[o + q];
+            nb.j[q] = NormJob{A.n, A.z, A.work, nullptr};
+            nb.first[q] = rb;
+            rb += red_blocks(A.n);
+            sb.j[q] = ShiftJob{A.n, red_blocks(A.n), A.work, A.norms_u, A.norms_z, A.h,
+                               A.u, A.z, A.out, A.sqrt_eps, A.sqrt_n};
+            sb.first[q] = eb;
+            eb += ew_blocks(A.n);
+        }
+        nb.first[c] = rb;
+        nb.nj = c;
+        sb.first[c] = eb;
+        sb.nj = c;
+        k_norm1_batched<<<rb, kThreads, 0, s>>>(nb);
+        k_shift_auto_batched<<<eb, kThreads, 0, s>>>(sb);
+    }
+}
+
+void cgs2_norm_batched(int nj, const Cgs2Args* a, hipStream_t s) {
+    std::vector<const Cgs2Args*> fused;
+    for (int q = 0; q < nj; ++q) {
+        const Cgs2Args& A = a[q];
+        if ((size_t)A.k * red_blocks(A.n) <= (size_t)kFusedPartials) {
+            fused.push_back(&A);
+            continue;
+        }
+        // many partials: the separate final-pass launches of cgs_pass
+        cgs_pass(A.n, A.k, A.V, A.ldv, A.Ep, A.Eu, A.h, A.w, A.hout1, A.work, s);
+        cgs_pass(A.n, A.k, A.V, A.ldv, nullptr, nullptr, nullptr, A.w, A.hout2, A.work, s);
+        norm_inf_2(A.n, A.w, A.norms, A.work, s);
+    }
+    const int nf = (int)fused.size();
+    for (int o = 0; o < nf; o += kMaxKJobs) {
+        const int c = std::min(kMaxKJobs, nf - o);
+        CgsBatch cb{};
+        NormBatch nb{};
+        int db = 0, eb = 0, rb = 0, kmax = 1;
+        std::vector<int> efirst(c + 1);
+        for (int q = 0; q < c; ++q) {
+            const Cgs2Args& A = *fused[o + q];
+            const int B = red_blocks(A.n);
+            cb.j[q] = CgsJob{A.n, A.k, B, A.V, A.ldv, A.Ep, A.Eu, A.h, A.w, A.hout1, A.work};
+            cb.first[q] = db;
+            db += B * A.k;
+            efirst[q] = eb;
+            eb += ew_blocks(A.n);
+            kmax = std::max(kmax, A.k);
+            nb.j[q] = NormJob{A.n, A.w, A.work, A.norms};
+            nb.first[q] = rb;
+            rb += B;
+        }
+        cb.first[c] = db;
+        cb.nj = c;
+        nb.first[c] = rb;
+        nb.nj = c;
+        CgsBatch eb1 = cb;
+        for (int q = 0; q <= c; ++q) eb1.first[q] = efirst[q];
+        efirst[c] = eb;
+        eb1.first[c] = eb;
+        const size_t lds = (size_t)kmax * sizeof(double);
+        // first pass: w = (Ep - Eu) / step, hout1 = V^T w, w -= V hout1
+        k_dots1_batched<<<db, kThreads, 0, s>>>(cb);
+        k_gemv_sub_dots_batched<<<eb, kThreads, lds, s>>>(eb1);
+        // second pass on w: hout2
+        for (int q = 0; q < c; ++q) {
+            cb.j[q].Ep = nullptr;
+            cb.j[q].Eu = nullptr;
+            cb.j[q].h = nullptr;
+            cb.j[q].hout = fused[o + q]->hout2;
+            eb1.j[q] = cb.j[q];
+        }
+        k_dots1_batched<<<db, kThreads, 0, s>>>(cb);
+        k_gemv_sub_dots_batched<<<eb, kThreads, lds, s>>>(eb1);
+        k_norm1_batched<<<rb, kThreads, 0, s>>>(nb);
+        k_norm2_batched<<<c, 64, 0, s>>>(nb);
     }
 }
 

@@ -151,7 +151,7 @@ void sw_server::start_task(Active& a, int precision) {
     a.zeta = c.take<double>((size_t)a.g.NM);
     void* tmem = c.p + ((c.off + 255) & ~size_t(255));
     a.task.reset(new SolveTask(a.g, a.prm, a.P, a.u, tmem, a.pin));
-    a.task->defer_apply = true;
+    a.task->deferred = true;
 }
 
 namespace {
@@ -328,18 +328,34 @@ void sw_server::run() {
             }
             if (!aP.empty())
                 precond_apply_batched((int)aP.size(), aP.data(), ab.data(), ax.data(), stream);
+            std::vector<ShiftArgs> shifts;
             for (auto& a : active) {
-                if (a->task->apply_pending) a->task->pre_rest(stream);
-                if (a->task->done()) continue;
-                geos.push_back(*a->task->req_g);
-                xs.push_back(a->task->req_x);
-                Es.push_back(a->task->req_E);
+                SolveTask& t = *a->task;
+                if (t.apply_pending) t.pre_rest(stream);
+                if (t.shift_pending) {
+                    shifts.push_back(t.shift_req);
+                    t.shift_pending = false;
+                }
+                if (t.done()) continue;
+                geos.push_back(*t.req_g);
+                xs.push_back(t.req_x);
+                Es.push_back(t.req_E);
             }
+            if (!shifts.empty()) shift_auto_batched((int)shifts.size(), shifts.data(), stream);
             if (!geos.empty())
                 residual_batched_enqueue((int)geos.size(), geos.data(), xs.data(), Es.data(),
                                          stream);
+            // Krylov steps leave their Gram-Schmidt passes, which run together
+            std::vector<Cgs2Args> cgs;
+            for (auto& a : active) {
+                SolveTask& t = *a->task;
+                if (t.done()) continue;
+                t.post(stream);
+                if (t.cgs_pending) cgs.push_back(t.cgs_req);
+            }
+            if (!cgs.empty()) cgs2_norm_batched((int)cgs.size(), cgs.data(), stream);
             for (auto& a : active)
-                if (!a->task->done()) a->task->post(stream);
+                if (a->task->cgs_pending) a->task->post_tail(stream);
             SW_HIP(hipStreamSynchronize(stream));
             for (auto& a : active) a->task->host(stream);
             std::vector<std::unique_ptr<Active>> keep;

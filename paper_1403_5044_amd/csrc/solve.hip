@@ -140,7 +140,7 @@ void SolveTask::pre(hipStream_t s) {
             } else if (pending_scale_ > 0.0) {
                 scale_copy(n_, 1.0 / pending_scale_, vj, vj, s);
             }
-            if (defer_apply) {
+            if (deferred) {
                 apply_pending = true;
                 apply_P = P_;
                 apply_b = vj;
@@ -184,8 +184,15 @@ void SolveTask::pre(hipStream_t s) {
 void SolveTask::pre_rest(hipStream_t s) {
     const int m = m_;
     apply_pending = false;
-    shift_auto(n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
-               hd_ + 2 * m + 8, xs_, red_, s);
+    const ShiftArgs a{n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
+                      hd_ + 2 * m + 8, xs_, red_};
+    if (deferred) {
+        shift_req = a;
+        shift_pending = true;
+    } else {
+        shift_auto(a.n, a.u, a.z, a.norms_u, a.sqrt_eps, a.sqrt_n, a.norms_z, a.h, a.out, a.work,
+                   s);
+    }
     req_x = xs_;
     req_E = Ejv_;
     req_g = &gin_;
@@ -219,11 +226,17 @@ void SolveTask::post(hipStream_t s) {
             maybe_inject(gin_.precision == SW_PREC_FP32 ? kInjectJvp32 : kInjectJvp64, s);
             double* vn = V_ + (size_t)(j_ + 1) * n_;
             // vn = J z by the difference quotient, then two Gram-Schmidt passes
-            cgs_pass(n_, j_ + 1, V_, n_, Ejv_, Ein_, hd_ + 2 * m + 8, vn, hd_, red_, s);
-            cgs_pass(n_, j_ + 1, V_, n_, nullptr, nullptr, nullptr, vn, hd_ + (m + 1), red_, s);
-            norm_inf_2(n_, vn, hd_ + 2 * m + 2, red_, s);
-            SW_HIP(hipMemcpyAsync(pin_out_, hd_, (2 * m + 4) * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
+            const Cgs2Args a{n_, j_ + 1, V_, (size_t)n_, Ejv_, Ein_, hd_ + 2 * m + 8, vn,
+                             hd_, hd_ + (m + 1), hd_ + 2 * m + 2, red_};
+            if (deferred) {
+                cgs_req = a;
+                cgs_pending = true;
+                break;
+            }
+            cgs_pass(n_, a.k, V_, a.ldv, a.Ep, a.Eu, a.h, vn, a.hout1, red_, s);
+            cgs_pass(n_, a.k, V_, a.ldv, nullptr, nullptr, nullptr, vn, a.hout2, red_, s);
+            norm_inf_2(n_, vn, a.norms, red_, s);
+            post_tail(s);
             break;
         }
         case Phase::Restart:
@@ -244,6 +257,13 @@ void SolveTask::post(hipStream_t s) {
         case Phase::Done:
             break;
     }
+}
+
+// the copy of a Krylov step's scalars (Gram-Schmidt coefficients and norms) to the host
+void SolveTask::post_tail(hipStream_t s) {
+    cgs_pending = false;
+    SW_HIP(hipMemcpyAsync(pin_out_, hd_, (2 * m_ + 4) * sizeof(double), hipMemcpyDeviceToHost,
+                          s));
 }
 
 void SolveTask::finish(int st) {

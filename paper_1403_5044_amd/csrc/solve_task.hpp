@@ -2,12 +2,15 @@
 // evaluation is an explicit request.  A driver calls, per step,
 //   pre(s)   enqueue the device work that produces the next state to evaluate
 //            (req_x) and names the output (req_E) and the precision (req_g);
-//            with defer_apply set, a Krylov step stops at its preconditioner apply
+//            with `deferred` set, a Krylov step stops at its preconditioner apply
 //            and names it in apply_P/apply_b/apply_x (apply_pending); the driver
-//            runs it, alone or batched with other tasks', then calls pre_rest(s);
+//            runs it, alone or batched with other tasks', then calls pre_rest(s),
+//            which leaves the shifted state's kernels in shift_req (shift_pending);
 //   <evaluate E(req_x) -> req_E, alone or batched with other tasks>;
 //   post(s)  enqueue the device work that consumes req_E and copies the
-//            scalars the host needs into pinned memory;
+//            scalars the host needs into pinned memory (deferred Krylov steps
+//            leave their Gram-Schmidt passes and norm in cgs_req (cgs_pending);
+//            the driver runs them, then calls post_tail(s) for the copy);
 //   <synchronise the stream>;
 //   host(s)  read those scalars and advance (Givens rotations, convergence
 //            tests, line-search decisions), possibly enqueueing device work.
@@ -73,17 +76,22 @@ class SolveTask {
     void pre(hipStream_t s);
     void pre_rest(hipStream_t s);
     void post(hipStream_t s);
+    void post_tail(hipStream_t s);
     void host(hipStream_t s);
 
     const double* req_x = nullptr;
     double* req_E = nullptr;
     const Geo* req_g = nullptr;
 
-    bool defer_apply = false;
+    bool deferred = false;
     bool apply_pending = false;
     const sw_precond* apply_P = nullptr;
     const double* apply_b = nullptr;
     double* apply_x = nullptr;
+    bool shift_pending = false;
+    ShiftArgs shift_req{};
+    bool cgs_pending = false;
+    Cgs2Args cgs_req{};
 
     int status = SW_ENOCONV;
     int newton = 0;

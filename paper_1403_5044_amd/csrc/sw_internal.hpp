@@ -167,6 +167,35 @@ void shift_auto(int n, const double* u, const double* z, const double* norms_u, 
 // quotient(), dots() and gemv_sub().
 void cgs_pass(int n, int k, const double* V, size_t ldv, const double* Ep, const double* Eu,
               const double* h, double* w, double* hout, double* work, hipStream_t s);
+// Batched forms for several independent solves (the server): every job's results are
+// bitwise those of its own shift_auto, or of cgs_pass with Ep, cgs_pass without, then
+// norm_inf_2(w) into norms; the jobs share the launches.
+struct ShiftArgs {
+    int n;
+    const double* u;
+    const double* z;
+    const double* norms_u;
+    double sqrt_eps, sqrt_n;
+    double* norms_z;
+    double* h;
+    double* out;
+    double* work;
+};
+void shift_auto_batched(int nj, const ShiftArgs* a, hipStream_t s);
+struct Cgs2Args {
+    int n, k;
+    const double* V;
+    size_t ldv;
+    const double* Ep;
+    const double* Eu;
+    const double* h;
+    double* w;
+    double* hout1;
+    double* hout2;
+    double* norms;
+    double* work;
+};
+void cgs2_norm_batched(int nj, const Cgs2Args* a, hipStream_t s);
 void residual_one(const Geo& g, const double* u, double* E, hipStream_t s);
 // work doubles for dots() with up to k vectors and for norm_inf_2()
 size_t reduce_work_doubles(int n, int k);

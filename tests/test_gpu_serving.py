@@ -74,6 +74,30 @@ def test_server_result_is_identical_alone_and_in_a_mix():
         assert r.status == 0
 
 
+def test_server_result_is_bitwise_the_direct_solve():
+    """The server runs each Krylov step's preconditioner apply, shifted state, Gram-Schmidt
+    passes and norm batched across the active solves. For requests whose F lies on the
+    grid of the server's preconditioner cache (so that its preconditioner is the one a
+    direct solve builds) the served zeta and iteration counts equal the direct solve's bit
+    for bit, in FP64 and mixed precision, with all requests in one mix."""
+    dom = tuple(DOM.values())
+    reqs = [(0.75, 0.2, 61, 21, *dom), (0.5, 0.3, 121, 41, *dom),
+            (1.0, 0.1, 31, 11, -8.0, 8.0, 8.0), (0.625, 0.15, 61, 21, *dom)]
+    for r in reqs:
+        assert round(r[0] / 0.025) * 0.025 == r[0]
+    for prec in ("fp64", "fp32"):
+        res = _serve(reqs, precision=prec, max_slots=8)
+        for r, (F, eps, N, M, x1, xN, yM) in zip(res, reqs):
+            assert r.status == 0 and r.used_fallback == 0
+            _, z, info = api.solve(F, eps, N, M, x1, xN, yM, precision=prec, q_blocks=5)
+            assert info.status == 0
+            log(f"{prec} {N}x{M} F={F}: server newton {r.newton_iters} gmres {r.gmres_iters}, "
+                f"direct {info.newton_iters} / {info.gmres_iters}, "
+                f"max |dzeta| {np.abs(host(z) - r.zeta).max():.1e}")
+            assert (r.newton_iters, r.gmres_iters) == (info.newton_iters, info.gmres_iters)
+            assert np.array_equal(host(z), r.zeta)
+
+
 def test_server_mixed_precision_matches_fp64_within_bound():
     r64 = _serve(REQS, precision="fp64", max_slots=8)
     r32 = _serve(REQS, precision="fp32", max_slots=8)

@@ -25,10 +25,14 @@ __global__ __launch_bounds__(kThreads) void k_axpby(int n, double a, const doubl
         out[t] = fma(a, x[t], b * y[t]);
 }
 
+__device__ __forceinline__ void scale_body(int n, double a, const double* __restrict__ x,
+                                           double* __restrict__ out, int bx, int nbx) {
+    for (int t = bx * kThreads + threadIdx.x; t < n; t += nbx * kThreads) out[t] = a * x[t];
+}
+
 __global__ __launch_bounds__(kThreads) void k_scale(int n, double a, const double* __restrict__ x,
                                                     double* __restrict__ out) {
-    for (int t = blockIdx.x * kThreads + threadIdx.x; t < n; t += gridDim.x * kThreads)
-        out[t] = a * x[t];
+    scale_body(n, a, x, out, blockIdx.x, gridDim.x);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -360,6 +364,20 @@ static_assert(sizeof(NormBatch) <= 4096 && sizeof(ShiftBatch) <= 4096 &&
                   sizeof(CgsBatch) <= 4096,
               "kernel argument block");
 
+struct ScaleBatch {
+    ScaleArgs j[kMaxKJobs];
+    int first[kMaxKJobs + 1];
+    int nj;
+};
+static_assert(sizeof(ScaleBatch) <= 4096, "kernel argument block");
+
+// blocks per job: ew_blocks(n)
+__global__ __launch_bounds__(kThreads) void k_scale_batched(const ScaleBatch b) {
+    const int p = job_of(b.first, b.nj);
+    const ScaleArgs& J = b.j[p];
+    scale_body(J.n, J.a, J.x, J.out, blockIdx.x - b.first[p], b.first[p + 1] - b.first[p]);
+}
+
 // blocks per job: red_blocks(n)
 __global__ __launch_bounds__(kThreads) void k_norm1_batched(const NormBatch b) {
     __shared__ double sh[kThreads / 64];
@@ -518,6 +536,22 @@ void cgs_pass(int n, int k, const double* V, size_t ldv, const double* w_in_Ep,
     } else {
         k_dots2<<<(k + 63) / 64, 64, 0, s>>>(k, B, work, hout);
         k_gemv_sub<<<ew_blocks(n), kThreads, 0, s>>>(n, k, V, ldv, hout, w);
+    }
+}
+
+void scale_copy_batched(int nj, const ScaleArgs* a, hipStream_t s) {
+    for (int o = 0; o < nj; o += kMaxKJobs) {
+        const int c = std::min(kMaxKJobs, nj - o);
+        ScaleBatch b{};
+        int eb = 0;
+        for (int q = 0; q < c; ++q) {
+            b.j[q] = a[o + q];
+            b.first[q] = eb;
+            eb += ew_blocks(a[o + q].n);
+        }
+        b.first[c] = eb;
+        b.nj = c;
+        k_scale_batched<<<eb, kThreads, 0, s>>>(b);
     }
 }
 

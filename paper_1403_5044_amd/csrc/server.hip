@@ -318,14 +318,21 @@ void sw_server::run() {
             std::vector<const sw_precond*> aP;
             std::vector<const double*> ab;
             std::vector<double*> ax;
+            std::vector<ScaleArgs> scales;
             for (auto& a : active) {
-                a->task->pre(stream);
-                if (a->task->apply_pending) {
-                    aP.push_back(a->task->apply_P);
-                    ab.push_back(a->task->apply_b);
-                    ax.push_back(a->task->apply_x);
+                SolveTask& t = *a->task;
+                t.pre(stream);
+                if (t.scale_pending) {
+                    scales.push_back(t.scale_req);
+                    t.scale_pending = false;
+                }
+                if (t.apply_pending) {
+                    aP.push_back(t.apply_P);
+                    ab.push_back(t.apply_b);
+                    ax.push_back(t.apply_x);
                 }
             }
+            if (!scales.empty()) scale_copy_batched((int)scales.size(), scales.data(), stream);
             if (!aP.empty())
                 precond_apply_batched((int)aP.size(), aP.data(), ab.data(), ax.data(), stream);
             std::vector<ShiftArgs> shifts;

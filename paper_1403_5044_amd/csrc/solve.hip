@@ -118,6 +118,17 @@ SolveTask::SolveTask(const Geo& g64, const SolveParams& prm, const sw_precond* P
 
 void SolveTask::pre(hipStream_t s) {
     const int m = m_;
+    if (fin_pending_) {
+        // the apply of the last cycle's update comes first; pre_rest() continues
+        apply_pending = true;
+        apply_P = P_;
+        apply_b = w_;
+        apply_x = z_;
+        req_x = nullptr;
+        req_E = nullptr;
+        req_g = nullptr;
+        return;
+    }
     switch (ph_) {
         case Phase::E0:
             if (prm_.init_flat) flat_state(g64_.NM, u_, s);
@@ -132,13 +143,17 @@ void SolveTask::pre(hipStream_t s) {
             break;
         case Phase::Krylov: {
             double* vj = V_ + (size_t)j_ * n_;
-            if (j_ == 0) {
-                if (restart_mode_)
-                    scale_copy(n_, 1.0 / beta_, w_, V_, s);
-                else
-                    scale_copy(n_, -1.0 / beta_, E_, V_, s);
-            } else if (pending_scale_ > 0.0) {
-                scale_copy(n_, 1.0 / pending_scale_, vj, vj, s);
+            ScaleArgs sc{0, 0.0, nullptr, nullptr};
+            if (j_ == 0)
+                sc = restart_mode_ ? ScaleArgs{n_, 1.0 / beta_, w_, V_}
+                                   : ScaleArgs{n_, -1.0 / beta_, E_, V_};
+            else if (pending_scale_ > 0.0)
+                sc = ScaleArgs{n_, 1.0 / pending_scale_, vj, vj};
+            if (sc.x && deferred) {
+                scale_req = sc;
+                scale_pending = true;
+            } else if (sc.x) {
+                scale_copy(sc.n, sc.a, sc.x, sc.out, s);
             }
             if (deferred) {
                 apply_pending = true;
@@ -154,13 +169,21 @@ void SolveTask::pre(hipStream_t s) {
             pre_rest(s);
             break;
         }
-        case Phase::Restart:
-            shift_auto(n_, u_, du_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
-                       hd_ + 2 * m + 8, xs_, red_, s);
+        case Phase::Restart: {
+            const ShiftArgs a{n_, u_, du_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_,
+                              hd_ + 2 * m + 6, hd_ + 2 * m + 8, xs_, red_};
+            if (deferred) {
+                shift_req = a;
+                shift_pending = true;
+            } else {
+                shift_auto(a.n, a.u, a.z, a.norms_u, a.sqrt_eps, a.sqrt_n, a.norms_z, a.h,
+                           a.out, a.work, s);
+            }
             req_x = xs_;
             req_E = Ejv_;
             req_g = &gin_;
             break;
+        }
         case Phase::Line:
             axpby(n_, 1.0, u_, lam_, du_, ut_, s);
             req_x = ut_;
@@ -184,6 +207,12 @@ void SolveTask::pre(hipStream_t s) {
 void SolveTask::pre_rest(hipStream_t s) {
     const int m = m_;
     apply_pending = false;
+    if (fin_pending_) {
+        fin_pending_ = false;
+        axpby(n_, 1.0, z_, fin_first_ ? 0.0 : 1.0, fin_first_ ? z_ : du_, du_, s);
+        pre(s);  // the Line or Restart state
+        return;
+    }
     const ShiftArgs a{n_, u_, z_, hd_ + 2 * m + 4, sqrt_eps_in_, sqrt_n_, hd_ + 2 * m + 6,
                       hd_ + 2 * m + 8, xs_, red_};
     if (deferred) {
@@ -316,11 +345,16 @@ void SolveTask::finish_cycle(hipStream_t s, bool converged) {
     for (int i = 0; i < k; ++i) pin_y_[i] = y_[i];
     SW_HIP(hipMemcpyAsync(hd_ + 2 * m + 10, pin_y_, k * sizeof(double), hipMemcpyHostToDevice, s));
     gemv_acc(n_, k, V_, n_, hd_ + 2 * m + 10, w_, s);
-    precond_apply(P_, w_, z_, s);
-    if (first_cycle_)
-        axpby(n_, 1.0, z_, 0.0, z_, du_, s);
-    else
-        axpby(n_, 1.0, z_, 1.0, du_, du_, s);
+    if (deferred) {
+        fin_pending_ = true;
+        fin_first_ = first_cycle_;
+    } else {
+        precond_apply(P_, w_, z_, s);
+        if (first_cycle_)
+            axpby(n_, 1.0, z_, 0.0, z_, du_, s);
+        else
+            axpby(n_, 1.0, z_, 1.0, du_, du_, s);
+    }
     first_cycle_ = false;
     if (converged || its_ >= prm_.max_gmres) {
         lam_ = 1.0;

@@ -2,8 +2,10 @@
 // evaluation is an explicit request.  A driver calls, per step,
 //   pre(s)   enqueue the device work that produces the next state to evaluate
 //            (req_x) and names the output (req_E) and the precision (req_g);
-//            with `deferred` set, a Krylov step stops at its preconditioner apply
-//            and names it in apply_P/apply_b/apply_x (apply_pending); the driver
+//            with `deferred` set, a Krylov step leaves the scaling of its basis
+//            vector in scale_req (scale_pending), stops at its preconditioner apply
+//            (as does the first pre() after a GMRES cycle, whose solution update
+//            needs an apply) and names it in apply_P/apply_b/apply_x (apply_pending); the driver
 //            runs it, alone or batched with other tasks', then calls pre_rest(s),
 //            which leaves the shifted state's kernels in shift_req (shift_pending);
 //   <evaluate E(req_x) -> req_E, alone or batched with other tasks>;
@@ -84,6 +86,8 @@ class SolveTask {
     const Geo* req_g = nullptr;
 
     bool deferred = false;
+    bool scale_pending = false;
+    ScaleArgs scale_req{};
     bool apply_pending = false;
     const sw_precond* apply_P = nullptr;
     const double* apply_b = nullptr;
@@ -132,6 +136,8 @@ class SolveTask {
     int j_ = 0, its_ = 0;
     double beta_ = 0.0, target_ = 0.0, pending_scale_ = 0.0;
     bool first_cycle_ = true, restart_mode_ = false;
+    // deferred: a GMRES cycle's update du (+)= P^{-1} w is left to the next pre()
+    bool fin_pending_ = false, fin_first_ = false;
 };
 
 // Pinned host blocks for task scalars, reused across tasks.

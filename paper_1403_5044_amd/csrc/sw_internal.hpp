@@ -168,8 +168,15 @@ void shift_auto(int n, const double* u, const double* z, const double* norms_u, 
 void cgs_pass(int n, int k, const double* V, size_t ldv, const double* Ep, const double* Eu,
               const double* h, double* w, double* hout, double* work, hipStream_t s);
 // Batched forms for several independent solves (the server): every job's results are
-// bitwise those of its own shift_auto, or of cgs_pass with Ep, cgs_pass without, then
-// norm_inf_2(w) into norms; the jobs share the launches.
+// bitwise those of its own scale_copy, shift_auto, or cgs_pass with Ep, cgs_pass
+// without, then norm_inf_2(w) into norms; the jobs share the launches.
+struct ScaleArgs {
+    int n;
+    double a;
+    const double* x;
+    double* out;
+};
+void scale_copy_batched(int nj, const ScaleArgs* a, hipStream_t s);
 struct ShiftArgs {
     int n;
     const double* u;

@@ -203,7 +203,9 @@ void SolveTask::pre(hipStream_t s) {
     }
 }
 
-// the rest of a Krylov step's pre() once z = P^{-1} v_j is enqueued: the shifted state
+// the rest of pre() once its apply z = P^{-1} b is enqueued: after a Krylov step's apply,
+// the shifted state; after a cycle-update apply, du (+)= z and then the Line or Restart
+// state's pre()
 void SolveTask::pre_rest(hipStream_t s) {
     const int m = m_;
     apply_pending = false;

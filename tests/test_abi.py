@@ -79,3 +79,12 @@ def test_request_footprint_query_is_host_only_and_monotone():
     # a request needs a preconditioner, and a preconditioner N <= 1024
     assert charge(1024, 5, 2)[0] == 0
     assert charge(1025, 5, 2)[0] == -1
+
+
+def test_batched_apply_argument_checks_run_on_the_host():
+    """An empty batch is a no-op and a negative count or a null array is rejected,
+    all before any device work."""
+    lib = _lib.load()
+    assert lib.shipwave_precond_apply_batched(0, None, None, None, None) == 0
+    assert lib.shipwave_precond_apply_batched(-1, None, None, None, None) == -1
+    assert lib.shipwave_precond_apply_batched(1, None, None, None, None) == -1

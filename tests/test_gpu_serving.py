@@ -99,9 +99,10 @@ def test_server_result_is_bitwise_the_direct_solve():
 
 
 def test_server_with_more_solves_than_one_batched_launch_takes():
-    """26 solves submitted at once (a batched Krylov launch takes 16 solves and an apply
-    round 24), with pairs of requests sharing a cached preconditioner (their applies go in
-    separate rounds): every served zeta equals its direct solve bit for bit."""
+    """26 solves submitted at once (a batched Krylov launch takes 16 solves, a batch of
+    applies up to 24), with pairs of requests sharing a cached preconditioner (their
+    applies go in separate batches): every served zeta equals its direct solve bit for
+    bit."""
     dom = tuple(DOM.values())
     reqs = []
     for k in range(26):

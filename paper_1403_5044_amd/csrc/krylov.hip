@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv_sub_dots(int n, int k, int B,
 }
 
 // ---- batched forms: job p takes blocks [first[p], first[p + 1]) of a 1-D grid ----
-constexpr int kMaxKJobs = 16;
+constexpr int kMaxKJobs = 32;
 
 __device__ __forceinline__ int job_of(const int* first, int nj) {
     int p = 0;

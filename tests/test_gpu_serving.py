@@ -99,24 +99,23 @@ def test_server_result_is_bitwise_the_direct_solve():
 
 
 def test_server_with_more_solves_than_one_batched_launch_takes():
-    """26 solves submitted at once (a batched Krylov launch takes 16 solves, a batch of
-    applies up to 24), with pairs of requests sharing a cached preconditioner (their
-    applies go in separate batches): every served zeta equals its direct solve bit for
-    bit."""
+    """40 solves submitted at once (a batched Krylov launch takes 32 solves, a batch of
+    applies up to 24), with requests sharing cached preconditioners (their applies go in
+    separate batches): every served zeta equals its direct solve bit for bit."""
     dom = tuple(DOM.values())
     reqs = []
-    for k in range(26):
+    for k in range(40):
         N, M = (31, 11) if k % 2 else (61, 21)
         reqs.append((0.025 * (20 + k % 9), 0.05 + 0.01 * k, N, M, *dom))
         assert round(reqs[-1][0] / 0.025) * 0.025 == reqs[-1][0]
-    res = _serve(reqs, precision="fp64", max_slots=32, hbm_budget_bytes=16e9)
+    res = _serve(reqs, precision="fp64", max_slots=48, hbm_budget_bytes=16e9)
     for r, (F, eps, N, M, x1, xN, yM) in zip(res, reqs):
         assert r.status == 0
         _, z, info = api.solve(F, eps, N, M, x1, xN, yM, q_blocks=5)
         assert info.status == 0
         assert (r.newton_iters, r.gmres_iters) == (info.newton_iters, info.gmres_iters)
         assert np.array_equal(host(z), r.zeta), (N, M, F, eps)
-    log(f"26 served solves equal their direct solves; mean latency "
+    log(f"40 served solves equal their direct solves; mean latency "
         f"{np.mean([r.t_done_s - r.t_submit_s for r in res]) * 1e3:.1f} ms")
 
 

@@ -1378,7 +1378,7 @@ __global__ __launch_bounds__(64) void k_apply_last(Geo g, const double* __restri
 
 // First or last step of several applies in one launch: workgroups [first[p], first[p+1])
 // take the block rows of request p, whose temporaries are work[p] (the handle's [4][NM]).
-constexpr int kMaxApplyBatch = 24;
+constexpr int kMaxApplyBatch = 32;
 struct ApplyBatch {
     Geo g[kMaxApplyBatch];
     double* work[kMaxApplyBatch];

@@ -99,8 +99,8 @@ def test_server_result_is_bitwise_the_direct_solve():
 
 
 def test_server_with_more_solves_than_one_batched_launch_takes():
-    """40 solves submitted at once (a batched Krylov launch takes 32 solves, a batch of
-    applies up to 24), with requests sharing cached preconditioners (their applies go in
+    """40 solves submitted at once (a batched Krylov launch or a batch of applies takes
+    up to 32 solves), with requests sharing cached preconditioners (their applies go in
     separate batches): every served zeta equals its direct solve bit for bit."""
     dom = tuple(DOM.values())
     reqs = []

@@ -61,7 +61,7 @@ def test_batched_apply_is_bitwise_the_single_apply():
     """Several preconditioners applied in shared launches give the bits of one apply each:
     super-row handles of different widths in one round, a handle used twice (second
     round), q = 0 and a one-block-row band (N = 700) through the single path, an
-    in-place request, and 25 distinct handles (a full round of 24, then a round of 1)."""
+    in-place request, and 33 distinct handles (a full round of 32, then a round of 1)."""
     dom = dict(x1=-16.0, xN=8.0, yM=12.0)
     pcs = [api.Preconditioner(api.Problem(61, 21, **dom, F=0.7, eps=0.1), 3),
            api.Preconditioner(api.Problem(121, 41, **dom, F=0.9, eps=0.1), 5),
@@ -70,9 +70,9 @@ def test_batched_apply_is_bitwise_the_single_apply():
            api.Preconditioner(api.Problem(41, 13, -8.0, 8.0, 6.0, F=0.9, eps=0.1,
                                           weights="simpson"), 2)]
     small = [api.Preconditioner(api.Problem(13, 5, -4.0, 4.0, 3.0, F=0.5 + 0.02 * k,
-                                            eps=0.1), 1 + k % 3) for k in range(25)]
+                                            eps=0.1), 1 + k % 3) for k in range(33)]
     rng = np.random.default_rng(11)
-    for reqs in ([0, 1, 0, 2, 3, 4, 1], list(range(len(pcs), len(pcs) + 25))):
+    for reqs in ([0, 1, 0, 2, 3, 4, 1], list(range(len(pcs), len(pcs) + 33))):
         allp = pcs + small
         sel = [allp[i] for i in reqs]
         bs = [dev(rng.standard_normal(P.prob.n_unknowns)) for P in sel]
